@@ -1,0 +1,393 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test names what it pins:
+  * exhaustive enumeration of discrete paths (the min over piecewise-constant
+    grid paths that eq. uN composes, written as a sum along the path as in
+    the proof of Theorem approx2, eq. raslebol) -- brute force on tiny grids;
+  * the Hamilton--Jacobi equation itself (eq. hjb with H = |p+P|^2/2 + V,
+    eq. HPV): one short step from smooth data must move u by -tau*H(grad u);
+  * the V = 0 closed form: N convex steps compose into one convolution with
+    the N-fold kernel (Theorem th:convex: slopes merge), in closed form for the
+    quadratic kernel;
+  * the axis splitting of Remark rk28 (joint n-D min == composed sweeps);
+  * monotonicity, commutation with constants, sup-norm non-expansiveness
+    (Remark after eq. uN; proof of Proposition prop:klm), grid translation
+    equivariance and reflection symmetry;
+  * the discrete effective Hamiltonian (Proposition prop:klm and the min-plus
+    eigenvalue remark): Karp's minimum cycle mean of the one-step min-plus
+    matrix, and H(0) = max V;
+  * the adjoint by central finite differences (the N-step map is piecewise
+    affine, so differences are exact away from argmin changes).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from paper_1210_4090_amd import workloads as wl
+
+
+def kin_ref(s, dx, tau, P):
+    """tau*K*(s dx/tau) for K(p) = (p+P)^2/2, i.e. K*(v) = v^2/2 - P v."""
+    v = s * dx / tau
+    return tau * (0.5 * v * v - P * v)
+
+
+# ---------------------------------------------------------------- paths ----
+def _paths_1d(u0, Vs, tau, P, R):
+    N = u0.shape[0]
+    dx = 1.0 / N
+    nsteps = len(Vs)
+    out = np.empty(N)
+    rng = range(-R, R + 1)
+    for i in range(N):
+        best = math.inf
+        for ss in itertools.product(rng, repeat=nsteps):
+            # ss[k] = displacement of step k (arrival - departure)
+            y = i
+            cost = 0.0
+            for k in range(nsteps - 1, -1, -1):
+                cost += kin_ref(ss[k], dx, tau, P) - tau * Vs[k][y % N]
+                y -= ss[k]
+            cost += u0[y % N]
+            best = min(best, cost)
+        out[i] = best
+    return out
+
+
+def test_paths_1d_time_dependent(orc):
+    """1-D, N=5, 3 steps, time-dependent V and P != 0 vs exhaustive paths."""
+    rng = np.random.default_rng(11)
+    N, tau, P, nsteps = 5, 0.5, 0.35, 3
+    u0 = rng.uniform(-0.1, 0.1, N)
+    basis = rng.uniform(-1, 1, (2, N))
+    tcoef = rng.uniform(-0.2, 0.2, (nsteps, 2))
+    Vs = [tcoef[k] @ basis for k in range(nsteps)]
+    got = orc.run(u0, tau, [P], nsteps, basis=basis, tcoef=tcoef)
+    ref = _paths_1d(u0, Vs, tau, P, R=7)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
+    # a wider path set changes nothing: the enumeration covered all minimisers
+    np.testing.assert_allclose(_paths_1d(u0, Vs[:2], tau, P, R=9),
+                               orc.run(u0, tau, [P], 2, basis=basis, tcoef=tcoef), atol=1e-14)
+
+
+def test_paths_1d_lifts_wrap(orc):
+    """Flat kernel (large tau): minimisers wrap around the torus several times."""
+    rng = np.random.default_rng(5)
+    N, tau, P = 4, 2.0, 0.9
+    u0 = rng.uniform(-1, 1, N)
+    V = [rng.uniform(-1, 1, N) for _ in range(2)]
+    basis = np.stack(V)
+    tcoef = np.eye(2)
+    got = orc.run(u0, tau, [P], 2, basis=basis, tcoef=tcoef)
+    ref = _paths_1d(u0, V, tau, P, R=14)
+    np.testing.assert_allclose(got, ref, atol=1e-13)
+
+
+def test_paths_2d(orc):
+    """2-D 3x3 grid, 2 steps, V changing in time, anisotropic P."""
+    rng = np.random.default_rng(7)
+    n0, n1 = 3, 3
+    tau, P = 0.6, (0.25, -0.4)
+    u0 = rng.uniform(-0.2, 0.2, (n1, n0))
+    basis = rng.uniform(-1, 1, (2, n1, n0))
+    tcoef = np.array([[0.3, 0.0], [0.0, -0.2]])
+    Vs = [tcoef[k, 0] * basis[0] + tcoef[k, 1] * basis[1] for k in range(2)]
+    got = orc.run(u0, tau, list(P), 2, basis=basis, tcoef=tcoef)
+    R = 4
+    disp = list(itertools.product(range(-R, R + 1), repeat=2))
+    ref = np.empty_like(u0)
+    for i1 in range(n1):
+        for i0 in range(n0):
+            best = math.inf
+            for d1 in disp:           # last step
+                for d0 in disp:       # first step
+                    y1 = (i0 - d1[0], i1 - d1[1])
+                    y0 = (y1[0] - d0[0], y1[1] - d0[1])
+                    c = u0[y0[1] % n1, y0[0] % n0]
+                    c += kin_ref(d0[0], 1 / n0, tau, P[0]) + kin_ref(d0[1], 1 / n1, tau, P[1])
+                    c -= tau * Vs[0][y1[1] % n1, y1[0] % n0]
+                    c += kin_ref(d1[0], 1 / n0, tau, P[0]) + kin_ref(d1[1], 1 / n1, tau, P[1])
+                    c -= tau * Vs[1][i1, i0]
+                    best = min(best, c)
+            ref[i1, i0] = best
+    np.testing.assert_allclose(got, ref, atol=1e-14)
+
+
+# ------------------------------------------------------------------ PDE ----
+def test_one_step_matches_hamilton_jacobi_1d(orc):
+    """Taylor expansion in time of the solution of u_t + (u_x+P)^2/2 + V = 0:
+    u(tau) = u0 - tau H + tau^2/2 (H_p^2 u_xx + H_p V_x) + O(tau^3), and the
+    scheme adds O(dx^2/tau) for smooth u0 (eq. hjb, eq. HPV)."""
+    N, tau, P = 16384, 5e-4, 0.7
+    x = np.arange(N) / N
+    tp = 2 * np.pi
+    u0 = np.sin(tp * x) + 0.3 * np.cos(2 * tp * x)
+    du = tp * np.cos(tp * x) - 0.6 * tp * np.sin(2 * tp * x)
+    ddu = -tp * tp * np.sin(tp * x) - 1.2 * tp * tp * np.cos(2 * tp * x)
+    V = np.cos(tp * x)
+    dV = -tp * np.sin(tp * x)
+    got = orc.step(u0, tau, [P], V)
+    Hp = du + P
+    pred = u0 - tau * (0.5 * Hp ** 2 + V) + 0.5 * tau * tau * (Hp * Hp * ddu + Hp * dV)
+    err = np.max(np.abs(got - pred))
+    assert err < 2e-5, err
+    # the same test with the opposite sign of P must fail by a wide margin
+    Hb = du - P
+    pred_bad = u0 - tau * (0.5 * Hb ** 2 + V) + 0.5 * tau * tau * (Hb * Hb * ddu + Hb * dV)
+    assert np.max(np.abs(got - pred_bad)) > 10 * err
+
+
+def test_one_step_matches_hamilton_jacobi_2d(orc):
+    """Axis a pairs with P_a and with the fastest-varying array index for a=0."""
+    n0, n1, tau = 4096, 2048, 5e-4
+    P = (0.3, -0.8)
+    tp = 2 * np.pi
+    x = (np.arange(n0) / n0)[None, :]
+    y = (np.arange(n1) / n1)[:, None]
+    u0 = 0.5 * np.sin(tp * x) + 0.2 * np.cos(tp * y) + 0 * x * y
+    ux = 0.5 * tp * np.cos(tp * x) + 0 * y
+    uy = -0.2 * tp * np.sin(tp * y) + 0 * x
+    uxx = -0.5 * tp * tp * np.sin(tp * x) + 0 * y
+    uyy = -0.2 * tp * tp * np.cos(tp * y) + 0 * x
+    V = np.cos(tp * (x + 2 * y))
+    Vx = -tp * np.sin(tp * (x + 2 * y))
+    Vy = 2 * Vx
+    got = orc.step(u0, tau, list(P), V)
+
+    def taylor(Pa, Pb):
+        hx, hy = ux + Pa, uy + Pb
+        u_tt = hx * hx * uxx + hy * hy * uyy + hx * Vx + hy * Vy
+        return u0 - tau * (0.5 * (hx ** 2 + hy ** 2) + V) + 0.5 * tau * tau * u_tt
+
+    # grid error of the coarser axis: at most dy^2 / (8 tau) = 6e-5
+    err = np.max(np.abs(got - taylor(P[0], P[1])))
+    assert err < 1.5e-4, err
+    for Pa, Pb in [(P[1], P[0]), (-P[0], P[1]), (P[0], -P[1])]:
+        assert np.max(np.abs(got - taylor(Pa, Pb))) > 5 * 1.5e-4
+
+
+# -------------------------------------------------------- closed form V=0 ----
+def kernel_power(D, N, dx, tau, P):
+    """N-fold min-plus self-convolution of the integer-sampled quadratic cost:
+    the N displacements that sum to D are as equal as possible (Theorem
+    th:convex: merging equal slope sequences), giving
+    dx^2 (D^2 + r (N - r)) / (2 tau N) - P D dx,  r = D mod N."""
+    D = np.asarray(D, dtype=np.int64)
+    r = np.mod(D, N)
+    return dx * dx * (D * D + r * (N - r)) / (2.0 * tau * N) - P * D * dx
+
+
+@pytest.mark.parametrize("P", [0.0, 0.3, -1.1])
+def test_v0_closed_form_1d(orc, P):
+    N, tau, steps = 64, 0.05, 7
+    u0 = wl.smooth_grid([N], seed=3) + 0.05 * wl.random_grid([N], seed=4)
+    got = orc.run(u0, tau, [P], steps)
+    dx = 1.0 / N
+    ref = np.empty(N)
+    J = np.arange(-8 * N, 9 * N)
+    for i in range(N):
+        ref[i] = np.min(u0[np.mod(J, N)] + kernel_power(i - J, steps, dx, tau, P))
+    np.testing.assert_allclose(got, ref, atol=2e-14)
+
+
+def test_v0_closed_form_2d(orc):
+    n0, n1, tau, steps, P = 16, 12, 0.08, 5, (0.4, -0.2)
+    u0 = wl.smooth_grid([n0, n1], seed=8)
+    got = orc.run(u0, tau, list(P), steps)
+    K0 = lambda D: kernel_power(D, steps, 1 / n0, tau, P[0])
+    K1 = lambda D: kernel_power(D, steps, 1 / n1, tau, P[1])
+    J0 = np.arange(-4 * n0, 5 * n0)
+    J1 = np.arange(-4 * n1, 5 * n1)
+    ref = np.empty_like(u0)
+    for i1 in range(n1):
+        for i0 in range(n0):
+            c = u0[np.mod(J1, n1)][:, np.mod(J0, n0)] + K0(i0 - J0)[None, :] + K1(i1 - J1)[:, None]
+            ref[i1, i0] = c.min()
+    np.testing.assert_allclose(got, ref, atol=2e-14)
+
+
+# ------------------------------------------------------- axis splitting ----
+@pytest.mark.parametrize("shape", [(12, 12), (5, 4, 6)])
+def test_joint_min_equals_composed_sweeps_bitwise(orc, shape):
+    """Remark rk28 with the association ((u + k_0) + k_1) + k_2: adding a
+    constant with rounding is nondecreasing, so the joint min and the
+    composed 1-D mins agree bit for bit."""
+    rng = np.random.default_rng(len(shape))
+    n = list(reversed(shape))
+    u = rng.uniform(-0.3, 0.3, shape)
+    V = rng.uniform(-1, 1, shape)
+    P = [0.2, -0.35, 0.1][: len(shape)]
+    a = orc.joint_step(u, 0.15, P, V)
+    b = orc.step(u, 0.15, P, V)
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------ properties ----
+def _rand_state(seed, shape=(24, 20)):
+    return wl.random_grid(list(reversed(shape)), seed, 0.5) + wl.smooth_grid(list(reversed(shape)), seed + 100)
+
+
+def test_monotone_constants_nonexpansive(orc):
+    tau, P = 0.05, [0.3, -0.2]
+    V = _rand_state(1)
+    u = _rand_state(2)
+    v = u + np.abs(_rand_state(3)) * 0.1
+    Tu = orc.run(u, tau, P, 3, V=V)
+    Tv = orc.run(v, tau, P, 3, V=V)
+    assert np.all(Tu <= Tv)                               # u <= v => T u <= T v
+    c = 0.625                                             # exactly representable
+    Tc = orc.run(u + c, tau, P, 3, V=V)
+    np.testing.assert_allclose(Tc, Tu + c, atol=1e-14)    # T(u + c) = T u + c
+    w = _rand_state(4)
+    Tw = orc.run(w, tau, P, 3, V=V)
+    assert np.max(np.abs(Tu - Tw)) <= np.max(np.abs(u - w)) + 1e-14
+
+
+def test_translation_equivariance_bitwise(orc):
+    tau, P = 0.05, [0.3, -0.2]
+    V = _rand_state(5)
+    u = _rand_state(6)
+    sh = (3, -5)
+    a = np.roll(orc.step(u, tau, P, V), sh, axis=(0, 1))
+    b = orc.step(np.roll(u, sh, axis=(0, 1)), tau, P, np.roll(V, sh, axis=(0, 1)))
+    assert np.array_equal(a, b)
+
+
+def test_reflection_symmetry_p0(orc):
+    """P = 0: the cost is even, so reflecting the data reflects the result."""
+    N = 40
+    u = wl.random_grid([N], 9) + wl.smooth_grid([N], 10)
+    V = wl.smooth_grid([N], 11)
+    refl = lambda a: np.roll(a[::-1], 1)                  # i -> -i mod N
+    a = refl(orc.run(u, 0.07, [0.0], 4, V=V))
+    b = orc.run(refl(u), 0.07, [0.0], 4, V=refl(V))
+    assert np.array_equal(a, b)
+
+
+def test_argmin_lowest_offset_and_value(orc):
+    """The reported offset attains the value; no smaller offset attains it."""
+    N, tau, P = 32, 0.3, 0.4
+    u = np.round(wl.random_grid([N], 12) * 8) / 8          # many exact ties
+    w, arg = orc.sweep(u, 0, tau, P)
+    dx = 1.0 / N
+    for i in range(N):
+        e = arg[i]
+        d = -e * dx
+        assert w[i] == u[(i + e) % N] + (((0.5 * d) * d) / tau - P * d)
+        for e2 in range(e - 3 * N, e):
+            d2 = -e2 * dx
+            assert u[(i + e2) % N] + (((0.5 * d2) * d2) / tau - P * d2) > w[i]
+
+
+def test_kinetic_table_equals_mechanical(orc):
+    """A caller table holding the mechanical cost reproduces the default path."""
+    N, tau, P = 48, 0.04, 0.25
+    u = wl.smooth_grid([N], 13) + 0.1 * wl.random_grid([N], 14)
+    half = 2 * N
+    tab = orc.kinetic(np.arange(-half, half + 1), 1.0 / N, tau, P)
+    a, aa = orc.sweep(u, 0, tau, P)
+    b, bb = orc.sweep(u, 0, tau, P, ktab=tab)
+    assert np.array_equal(a, b) and np.array_equal(aa, bb)
+
+
+# ------------------------------------------------- effective Hamiltonian ----
+def _bracket(orc, u0, tau, P, V, T):
+    ell = int(round(1 / tau))
+    u = orc.run(u0, tau, P, int(round(T / tau)) - ell, V=V)
+    u2 = orc.run(u, tau, P, ell, V=V)
+    d = u2 - u
+    return -d.max(), -d.min()
+
+
+def test_hbar_p0_equals_max_v(orc):
+    """P = 0, static V: staying at argmax V costs -tau max V per step and no
+    path does better, so the discrete effective Hamiltonian is max V."""
+    N = 64
+    V = wl.smooth_grid([N], 21)
+    lo, hi = _bracket(orc, np.zeros(N), 0.1, [0.0], V, 30.0)
+    assert abs(lo - V.max()) < 1e-11 and abs(hi - V.max()) < 1e-11
+
+
+def _karp(A):
+    """Karp's minimum cycle mean of a complete weighted digraph A[y][x]."""
+    n = A.shape[0]
+    D = np.full((n + 1, n), np.inf)
+    D[0, :] = 0.0
+    for k in range(1, n + 1):
+        D[k] = np.min(D[k - 1][:, None] + A, axis=0)
+    best = np.inf
+    for v in range(n):
+        worst = -np.inf
+        for k in range(n):
+            if np.isfinite(D[k, v]):
+                worst = max(worst, (D[n, v] - D[k, v]) / (n - k))
+        best = min(best, worst)
+    return best
+
+
+def test_hbar_karp_min_cycle_mean(orc):
+    """Min-plus eigenvalue remark: -tau * Hbar is the minimum cycle mean of
+    the one-step matrix A[y][x] = min over lifts of k(x - y) - tau V(x)."""
+    N, tau, P = 7, 0.25, 0.83
+    rng = np.random.default_rng(31)
+    V = rng.uniform(-1, 1, N)
+    dx = 1.0 / N
+    A = np.empty((N, N))
+    for y in range(N):
+        for x in range(N):
+            m = np.arange(-40, 41)
+            A[y, x] = np.min(kin_ref(x - y + m * N, dx, tau, P)) - tau * V[x]
+    hbar = -_karp(A) / tau
+    lo, hi = _bracket(orc, rng.uniform(-1, 1, N), tau, [P], V, 60.0)
+    assert lo - 1e-10 <= hbar <= hi + 1e-10
+    assert hi - lo < 1e-9
+
+
+# ---------------------------------------------------------------- adjoint ----
+def test_adjoint_finite_differences(orc):
+    n0, n1, tau, steps, P = 20, 16, 0.04, 6, (0.3, 0.1)
+    kv, kinds = wl.half_plane_basis(4)
+    basis = wl.basis_tables([n0, n1], kv, kinds)
+    rng = np.random.default_rng(41)
+    coef = rng.standard_normal(basis.shape[0]) * 0.3
+    u0 = wl.smooth_grid([n0, n1], 42)
+    target = wl.smooth_grid([n0, n1], 43) * 0.1
+
+    def loss(u0_, c_):
+        V = orc.potential(basis, c_)
+        uT = orc.run(u0_, tau, list(P), steps, V=V)
+        return np.mean((uT - target) ** 2), uT
+
+    L0, uT = loss(u0, coef)
+    g = 2.0 * (uT - target) / uT.size
+    uT2, gu, gc = orc.adjoint(u0, tau, list(P), steps, basis, coef, g)
+    np.testing.assert_array_equal(uT, uT2)
+    eps = 1e-6
+    for m in range(basis.shape[0]):
+        cp, cm = coef.copy(), coef.copy()
+        cp[m] += eps
+        cm[m] -= eps
+        fd = (loss(u0, cp)[0] - loss(u0, cm)[0]) / (2 * eps)
+        assert abs(fd - gc[m]) <= 1e-6 * max(1.0, abs(gc).max()), (m, fd, gc[m])
+    for (i1, i0) in [(0, 0), (3, 7), (15, 19), (8, 11)]:
+        up, um = u0.copy(), u0.copy()
+        up[i1, i0] += eps
+        um[i1, i0] -= eps
+        fd = (loss(up, coef)[0] - loss(um, coef)[0]) / (2 * eps)
+        assert abs(fd - gu[i1, i0]) <= 1e-6 * max(1e-3, abs(gu).max()), (i1, i0, fd, gu[i1, i0])
+
+
+def test_adjoint_invariants(orc):
+    """Each scatter conserves the sum; a constant mode's gradient is
+    -N tau sum(dL/du(T))."""
+    n0, n1, tau, steps, P = 12, 10, 0.05, 5, (0.2, -0.3)
+    kv, kinds = wl.half_plane_basis(2)
+    basis = np.concatenate([np.ones((1, n1, n0)), wl.basis_tables([n0, n1], kv, kinds)])
+    coef = np.array([0.5, 0.3, -0.2, 0.1, 0.25])
+    u0 = wl.smooth_grid([n0, n1], 51)
+    g = wl.random_grid([n0, n1], 52)
+    uT, gu, gc = orc.adjoint(u0, tau, list(P), steps, basis, coef, g)
+    assert abs(gu.sum() - g.sum()) < 1e-12
+    assert abs(gc[0] - (-steps * tau * g.sum())) < 1e-12
