@@ -1,0 +1,543 @@
+// Host side of the C ABI declared in include/lo.h: plan construction (kinetic
+// tables of Section 2.3's cost, tau*V, window margins), the time loop of
+// eq. uN, HIP graphs for it, diagnostics.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "lo_internal.h"
+
+using namespace lo;
+
+struct lo_plan_s {
+    lo_desc d;
+    int ndim = 0;
+    int64_t n[kMaxDim] = {1, 1, 1};
+    int64_t npts = 0;
+    double dx[kMaxDim] = {0, 0, 0};
+    int64_t kcap[kMaxDim] = {0, 0, 0};
+    std::vector<double> hkt[kMaxDim];   // host kinetic tables, index s + kcap
+    double* dkt[kMaxDim] = {nullptr, nullptr, nullptr};
+    double kmaxabs[kMaxDim] = {0, 0, 0};
+    double kzero_drop[kMaxDim] = {0, 0, 0};   // k(0) - min_s k(s), rounded up
+    bool user_table[kMaxDim] = {false, false, false};
+    int kind[kMaxDim] = {kKindRow, kKindTile, kKindTile};
+    int halo[kMaxDim] = {0, 0, 0};
+    int tile_rows[kMaxDim] = {0, 0, 0};
+    // potential
+    int nmodes = 0;
+    const double* basis = nullptr;
+    std::vector<double> coef;
+    std::vector<double> tcoef;
+    int64_t ntcoef = 0;
+    double* dcoef = nullptr;     // [nmodes] static coefficients
+    double* dtcoef = nullptr;    // [ntcoef][nmodes]
+    double* dhv = nullptr;       // tau*V (static) or the current step's tau*V(t_n)
+    bool has_v = false;
+    bool time_dep = false;
+    double dvf[kMaxDim] = {0, 0, 0}, dvb[kMaxDim] = {0, 0, 0};
+    double hvmax = 0.0;
+    // work
+    double* scratch = nullptr;
+    uint64_t* stats = nullptr;   // kSlots * kSlotWords
+    uint32_t* flags = nullptr;   // kFlagWords
+    uint32_t hflags[kFlagWords] = {0};
+    bool have_diag = false;
+    bool had_argmin = false;
+    // graph cache for lo_run
+    hipGraphExec_t gexec = nullptr;
+    double* g_u = nullptr;
+    int64_t g_phase = -1;
+    int g_steps = 0;
+    hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+uint64_t host_enc_neg_inf() { return ~(uint64_t)0xFFF0000000000000ull; }
+
+double host_dec(uint64_t k)
+{
+    const uint64_t sign = 0x8000000000000000ull;
+    uint64_t b = (k & sign) ? (k & ~sign) : ~k;
+    double x;
+    memcpy(&x, &b, 8);
+    return x;
+}
+
+// tau K*(s dx / tau) for K(p) = (p + P)^2 / 2, evaluated in a fixed order.
+double mech_cost(int64_t s, double dx, double tau, double P)
+{
+    const double d = (double)s * dx;
+    const double a = 0.5 * d;
+    const double b = a * d;
+    const double c = b / tau;
+    const double e = P * d;
+    return c - e;
+}
+
+#define HIPCHK(x)                                 \
+    do {                                          \
+        hipError_t _e = (x);                      \
+        if (_e != hipSuccess) return LO_ERR_HIP;  \
+    } while (0)
+
+lo_status alloc(void** p, size_t bytes)
+{
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return LO_ERR_OOM;
+    }
+    return LO_OK;
+}
+
+void free_plan(lo_plan_t p)
+{
+    if (!p) return;
+    for (int a = 0; a < kMaxDim; a++)
+        if (p->dkt[a]) (void)hipFree(p->dkt[a]);
+    if (p->dcoef) (void)hipFree(p->dcoef);
+    if (p->dtcoef) (void)hipFree(p->dtcoef);
+    if (p->dhv) (void)hipFree(p->dhv);
+    if (p->scratch) (void)hipFree(p->scratch);
+    if (p->stats) (void)hipFree(p->stats);
+    if (p->flags) (void)hipFree(p->flags);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    delete p;
+}
+
+lo_status build_tables(lo_plan_t p)
+{
+    for (int a = 0; a < p->ndim; a++) {
+        std::vector<double>& t = p->hkt[a];
+        if (p->d.kstar_tab[a]) {
+            const int64_t half = p->d.kstar_half[a];
+            if (half < 1 || half > (1 << 20)) return LO_ERR_INVALID;
+            p->kcap[a] = half;
+            p->user_table[a] = true;
+            t.assign(p->d.kstar_tab[a], p->d.kstar_tab[a] + 2 * half + 1);
+        } else {
+            // every displacement the window can reach on the lifted line: two periods
+            const int64_t cap = std::min<int64_t>(32767, std::max<int64_t>(64, 2 * p->n[a]));
+            p->kcap[a] = cap;
+            t.resize(2 * cap + 1);
+            for (int64_t s = -cap; s <= cap; s++) t[s + cap] = mech_cost(s, p->dx[a], p->d.tau, p->d.P[a]);
+        }
+        // hypothesis (i): discretely convex (differences nondecreasing), finite
+        double mx = 0.0;
+        for (size_t i = 0; i < t.size(); i++) {
+            if (!std::isfinite(t[i])) return LO_ERR_INVALID;
+            mx = std::max(mx, fabs(t[i]));
+        }
+        for (size_t i = 2; i < t.size(); i++)
+            if (!((t[i] - t[i - 1]) >= (t[i - 1] - t[i - 2]))) return LO_ERR_INVALID;
+        p->kmaxabs[a] = mx;
+        const double k0 = t[p->kcap[a]];
+        const double kmin = *std::min_element(t.begin(), t.end());
+        p->kzero_drop[a] = (k0 - kmin) * (1.0 + 0x1p-40) + 0x1p-60;
+        lo_status st = alloc((void**)&p->dkt[a], sizeof(double) * t.size());
+        if (st) return st;
+        HIPCHK(hipMemcpy(p->dkt[a], t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
+    }
+    return LO_OK;
+}
+
+// Bound of tau*(V(x) - V(x + e_a)) and tau*(V(x + e_a) - V(x)) from the hv table.
+lo_status add_potential_margins(lo_plan_t p, const double* hv, bool first)
+{
+    double* d6 = nullptr;
+    lo_status st = alloc((void**)&d6, sizeof(uint64_t) * 32);
+    if (st) return st;
+    std::vector<uint64_t> init(32, host_enc_neg_inf());
+    HIPCHK(hipMemcpy(d6, init.data(), sizeof(uint64_t) * 32, hipMemcpyHostToDevice));
+    if (launch_potential_diffs(hv, p->ndim, p->n, d6, nullptr) != hipSuccess) {
+        (void)hipFree(d6);
+        return LO_ERR_HIP;
+    }
+    if (launch_stats(hv, p->ndim, p->n, (uint64_t*)d6 + 16, nullptr) != hipSuccess) {
+        (void)hipFree(d6);
+        return LO_ERR_HIP;
+    }
+    uint64_t h[32];
+    hipError_t e = hipMemcpy(h, d6, sizeof(uint64_t) * 32, hipMemcpyDeviceToHost);
+    (void)hipFree(d6);
+    if (e != hipSuccess) return LO_ERR_HIP;
+    for (int a = 0; a < p->ndim; a++) {
+        double f = host_dec(h[a]), b = host_dec(h[3 + a]);
+        f = f * (1.0 + 0x1p-40) + 0x1p-60;
+        b = b * (1.0 + 0x1p-40) + 0x1p-60;
+        if (first) {
+            p->dvf[a] = f;
+            p->dvb[a] = b;
+        } else {
+            p->dvf[a] = std::max(p->dvf[a], f);
+            p->dvb[a] = std::max(p->dvb[a], b);
+        }
+    }
+    double m = host_dec(h[16 + 6]);
+    p->hvmax = first ? m : std::max(p->hvmax, m);
+    return LO_OK;
+}
+
+lo_status setup_potential(lo_plan_t p, const lo_potential* V)
+{
+    if (!V) return LO_OK;
+    const size_t bytes = sizeof(double) * (size_t)p->npts;
+    if (V->table) {
+        lo_status st = alloc((void**)&p->dhv, bytes);
+        if (st) return st;
+        HIPCHK(launch_scale(V->table, p->d.tau, p->npts, p->dhv, nullptr));
+        p->has_v = true;
+    } else if (V->nmodes > 0) {
+        if (!V->basis) return LO_ERR_INVALID;
+        p->nmodes = V->nmodes;
+        p->basis = V->basis;
+        lo_status st = alloc((void**)&p->dhv, bytes);
+        if (st) return st;
+        if (V->tcoef) {
+            if (V->ntcoef < 1) return LO_ERR_INVALID;
+            p->time_dep = true;
+            p->ntcoef = V->ntcoef;
+            p->tcoef.assign(V->tcoef, V->tcoef + V->ntcoef * V->nmodes);
+            st = alloc((void**)&p->dtcoef, sizeof(double) * p->tcoef.size());
+            if (st) return st;
+            HIPCHK(hipMemcpy(p->dtcoef, p->tcoef.data(), sizeof(double) * p->tcoef.size(),
+                             hipMemcpyHostToDevice));
+        } else {
+            if (!V->coef) return LO_ERR_INVALID;
+            p->coef.assign(V->coef, V->coef + V->nmodes);
+            st = alloc((void**)&p->dcoef, sizeof(double) * p->nmodes);
+            if (st) return st;
+            HIPCHK(hipMemcpy(p->dcoef, p->coef.data(), sizeof(double) * p->nmodes, hipMemcpyHostToDevice));
+            HIPCHK(launch_synth_hv(p->basis, p->dcoef, p->nmodes, p->npts, p->d.tau, p->dhv, nullptr));
+        }
+        p->has_v = true;
+    }
+    if (!p->has_v) return LO_OK;
+    if (p->time_dep) {
+        for (int64_t k = 0; k < p->ntcoef; k++) {
+            HIPCHK(launch_synth_hv(p->basis, p->dtcoef + k * p->nmodes, p->nmodes, p->npts, p->d.tau, p->dhv,
+                                   nullptr));
+            lo_status st = add_potential_margins(p, p->dhv, k == 0);
+            if (st) return st;
+        }
+    } else {
+        lo_status st = add_potential_margins(p, p->dhv, true);
+        if (st) return st;
+    }
+    HIPCHK(hipDeviceSynchronize());
+    return LO_OK;
+}
+
+// LDS bytes of the tile kernel for R targets, halo H, 16 lines
+size_t tile_lds(int R, int H) { return sizeof(double) * ((size_t)(R + 2 * H + 1) * 16 + (size_t)(R + 1) * 16); }
+
+void choose_kernels(lo_plan_t p)
+{
+    int dev = 0, lds_max = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        lds_max = 65536;
+    (void)hipGetLastError();
+    const size_t budget = std::min<size_t>((size_t)lds_max, 64 * 1024);
+    for (int a = 0; a < p->ndim; a++) {
+        const int64_t N = p->n[a];
+        if (a == 0 && (size_t)(N + 2) * sizeof(double) <= budget) {
+            p->kind[a] = kKindRow;
+            int64_t H = std::min<int64_t>(N, 1024);
+            while (H > 1 && (size_t)(N + 2 * H) * sizeof(double) > budget) H /= 2;
+            p->halo[a] = (int)std::max<int64_t>(H, 1);
+            p->tile_rows[a] = 0;
+        } else {
+            p->kind[a] = kKindTile;
+            int R = (int)std::min<int64_t>(N, 128);
+            int H = (int)std::min<int64_t>(N, 256);
+            while (H > 8 && tile_lds(R, H) > budget) H -= 8;
+            p->tile_rows[a] = R;
+            p->halo[a] = H;
+        }
+    }
+}
+
+double slack_extra(lo_plan_t p)
+{
+    double s = p->hvmax;
+    for (int a = 0; a < p->ndim; a++) s += p->kmaxabs[a];
+    return s;
+}
+
+uint64_t* slot(lo_plan_t p, int64_t n) { return p->stats + (size_t)(((n % kSlots) + kSlots) % kSlots) * kSlotWords; }
+
+// Buffers of the sweeps of one step: in/out per axis so that the result lands in u.
+void sweep_buffers(lo_plan_t p, double* u, double* in[kMaxDim], double* out[kMaxDim])
+{
+    int tiles = 0;
+    for (int a = 0; a < p->ndim; a++) tiles += p->kind[a] == kKindTile;
+    bool flip_row = (tiles % 2) == 1;  // one row sweep goes out of place to keep the parity
+    double* cur = u;
+    for (int a = 0; a < p->ndim; a++) {
+        in[a] = cur;
+        bool oop = p->kind[a] == kKindTile || (flip_row && p->kind[a] == kKindRow);
+        if (p->kind[a] == kKindRow && flip_row) flip_row = false;
+        double* nxt = oop ? (cur == u ? p->scratch : u) : cur;
+        out[a] = nxt;
+        cur = nxt;
+    }
+}
+
+lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipStream_t s)
+{
+    const double* hv = p->has_v ? p->dhv : nullptr;
+    if (p->time_dep) {
+        if (n < 0 || n >= p->ntcoef) return LO_ERR_INVALID;
+        HIPCHK(launch_synth_hv(p->basis, p->dtcoef + n * p->nmodes, p->nmodes, p->npts, p->d.tau, p->dhv, s));
+    }
+    double* in[kMaxDim];
+    double* out[kMaxDim];
+    sweep_buffers(p, u, in, out);
+    const double sx = slack_extra(p);
+    for (int a = 0; a < p->ndim; a++) {
+        SweepArgs A;
+        memset(&A, 0, sizeof(A));
+        A.g.n = p->n[a];
+        A.g.stride = 1;
+        for (int b = 0; b < a; b++) A.g.stride *= p->n[b];
+        A.g.nlines = p->npts / p->n[a];
+        A.kin.k = p->dkt[a] + p->kcap[a];
+        A.kin.kcap = p->kcap[a];
+        A.axis = a;
+        A.ndim = p->ndim;
+        A.wfix = p->d.window[a];
+        A.slack_extra = sx;
+        A.dv_fwd = p->dvf[a];
+        A.dv_bwd = p->dvb[a];
+        // a sweep raises the max by at most k(0) and lowers the min by at most -min k
+        for (int b = 0; b < a; b++) A.osc_extra += p->kzero_drop[b];
+        A.kind = p->kind[a];
+        A.cap_is_error = p->user_table[a] ? 0 : 1;
+        if (p->kind[a] == kKindTile) {
+            A.stats_in = slot(p, n);
+            A.stats_out = slot(p, n + 1);
+        }
+        A.stats_clear = a == 0 ? slot(p, n + 2) : nullptr;
+        A.flags = p->flags;
+        A.hv = a == p->ndim - 1 ? hv : nullptr;
+        A.argmin = argmin ? argmin + (size_t)a * p->npts : nullptr;
+        A.halo = p->halo[a];
+        A.tile_rows = p->tile_rows[a];
+        HIPCHK(launch_sweep(p->d.method, in[a], out[a], A, s));
+    }
+    if (out[p->ndim - 1] != u)
+        HIPCHK(hipMemcpyAsync(u, out[p->ndim - 1], sizeof(double) * p->npts, hipMemcpyDeviceToDevice, s));
+    return LO_OK;
+}
+
+lo_status prologue(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
+{
+    HIPCHK(hipMemsetAsync(p->flags, 0, sizeof(uint32_t) * kFlagWords, s));
+    HIPCHK(launch_clear_slots(p->stats, s));
+    HIPCHK(launch_stats(u, p->ndim, p->n, slot(p, n0), s));
+    return LO_OK;
+}
+
+lo_status finish(lo_plan_t p, hipStream_t s, bool argmin)
+{
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(p->hflags, p->flags, sizeof(uint32_t) * kFlagWords, hipMemcpyDeviceToHost));
+    p->have_diag = true;
+    p->had_argmin = argmin;
+    if (p->hflags[0] & (kErrWindowCap | kErrWindowEdge)) return LO_ERR_WINDOW;
+    if (p->hflags[0] & kErrArgRange) return LO_ERR_UNSUPPORTED;
+    return LO_OK;
+}
+
+bool graphable(lo_plan_t p) { return !(p->d.flags & LO_FLAG_NO_GRAPH) && !p->time_dep; }
+
+}  // namespace
+
+extern "C" {
+
+const char* lo_status_string(lo_status s)
+{
+    switch (s) {
+    case LO_OK: return "ok";
+    case LO_ERR_INVALID: return "invalid argument";
+    case LO_ERR_UNSUPPORTED: return "unsupported";
+    case LO_ERR_OOM: return "out of device memory";
+    case LO_ERR_HIP: return "HIP runtime error";
+    case LO_ERR_WINDOW: return "window saturated or beyond capacity";
+    }
+    return "unknown status";
+}
+
+lo_status lo_plan(const lo_desc* desc, const lo_potential* V, lo_plan_t* out)
+{
+    if (!desc || !out) return LO_ERR_INVALID;
+    *out = nullptr;
+    if (desc->ndim < 1 || desc->ndim > kMaxDim) return LO_ERR_INVALID;
+    if (!(desc->tau > 0) || !std::isfinite(desc->tau)) return LO_ERR_INVALID;
+    if (desc->method != LO_BRUTE && desc->method != LO_FAST) return LO_ERR_INVALID;
+    lo_plan_t p = new (std::nothrow) lo_plan_s();
+    if (!p) return LO_ERR_OOM;
+    p->d = *desc;
+    p->ndim = desc->ndim;
+    p->npts = 1;
+    for (int a = 0; a < p->ndim; a++) {
+        if (desc->n[a] < 3 || desc->n[a] > (1ll << 31)) {
+            free_plan(p);
+            return LO_ERR_INVALID;
+        }
+        if (!(desc->period[a] > 0) || !std::isfinite(desc->period[a]) || !std::isfinite(desc->P[a]) ||
+            desc->window[a] < 0) {
+            free_plan(p);
+            return LO_ERR_INVALID;
+        }
+        p->n[a] = desc->n[a];
+        p->npts *= desc->n[a];
+        p->dx[a] = desc->period[a] / (double)desc->n[a];
+    }
+    if (p->npts > (1ll << 34)) {
+        free_plan(p);
+        return LO_ERR_INVALID;
+    }
+    lo_status st = build_tables(p);
+    if (!st) {
+        for (int a = 0; a < p->ndim; a++)
+            if (desc->window[a] > 0 && desc->window[a] > p->kcap[a]) st = LO_ERR_INVALID;
+    }
+    if (!st) st = alloc((void**)&p->scratch, sizeof(double) * (size_t)p->npts);
+    if (!st) st = alloc((void**)&p->stats, sizeof(uint64_t) * kSlots * kSlotWords);
+    if (!st) st = alloc((void**)&p->flags, sizeof(uint32_t) * kFlagWords);
+    if (!st) st = setup_potential(p, V);
+    if (st) {
+        free_plan(p);
+        return st;
+    }
+    choose_kernels(p);
+    *out = p;
+    return LO_OK;
+}
+
+lo_status lo_plan_destroy(lo_plan_t p)
+{
+    if (!p) return LO_ERR_INVALID;
+    free_plan(p);
+    return LO_OK;
+}
+
+lo_status lo_set_coef(lo_plan_t p, const double* coef)
+{
+    if (!p || !coef || p->nmodes <= 0 || p->time_dep || !p->dcoef) return LO_ERR_INVALID;
+    p->coef.assign(coef, coef + p->nmodes);
+    HIPCHK(hipMemcpy(p->dcoef, coef, sizeof(double) * p->nmodes, hipMemcpyHostToDevice));
+    HIPCHK(launch_synth_hv(p->basis, p->dcoef, p->nmodes, p->npts, p->d.tau, p->dhv, nullptr));
+    lo_status st = add_potential_margins(p, p->dhv, true);
+    if (st) return st;
+    HIPCHK(hipDeviceSynchronize());
+    return LO_OK;
+}
+
+lo_status lo_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, void* stream)
+{
+    if (!p || !u) return LO_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    lo_status st = prologue(p, u, n, s);
+    if (st) return st;
+    st = enqueue_step(p, u, n, argmin, s);
+    if (st) return st;
+    return finish(p, s, argmin != nullptr);
+}
+
+lo_status lo_run(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckpt_every, double* ckpt,
+                 void* stream)
+{
+    if (!p || !u || nsteps < 0) return LO_ERR_INVALID;
+    if (ckpt && ckpt_every <= 0) return LO_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    lo_status st = prologue(p, u, n0, s);
+    if (st) return st;
+    const bool use_graph = graphable(p) && !ckpt && nsteps >= 6;
+    int64_t done = 0;
+    if (use_graph) {
+        // one graph holds G steps; the stats slots repeat with period 3, so a
+        // graph built for phase n0 % 3 replays for every block of G steps
+        const int G = 30;
+        const int64_t phase = ((n0 % kSlots) + kSlots) % kSlots;
+        if (p->gexec && (p->g_u != u || p->g_phase != phase || p->g_steps != G)) {
+            (void)hipGraphExecDestroy(p->gexec);
+            p->gexec = nullptr;
+        }
+        if (!p->gexec && nsteps >= G) {
+            if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+            lo_status cst = LO_OK;
+            for (int k = 0; k < G && !cst; k++) cst = enqueue_step(p, u, n0 + k, nullptr, p->cap_stream);
+            hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
+            if (cst) {
+                if (g) (void)hipGraphDestroy(g);
+                return cst;
+            }
+            HIPCHK(ce);
+            hipError_t ie = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPCHK(ie);
+            p->g_u = u;
+            p->g_phase = phase;
+            p->g_steps = G;
+        }
+        if (p->gexec) {
+            while (nsteps - done >= G) {
+                HIPCHK(hipGraphLaunch(p->gexec, s));
+                done += G;
+            }
+        }
+    }
+    for (; done < nsteps; done++) {
+        if (ckpt && done % ckpt_every == 0)
+            HIPCHK(hipMemcpyAsync(ckpt + (size_t)(done / ckpt_every) * p->npts, u, sizeof(double) * p->npts,
+                                  hipMemcpyDeviceToDevice, s));
+        st = enqueue_step(p, u, n0 + done, nullptr, s);
+        if (st) return st;
+    }
+    return finish(p, s, false);
+}
+
+lo_status lo_last_diag(lo_plan_t p, int32_t* window_used, int32_t* max_abs_offset)
+{
+    if (!p || !p->have_diag) return LO_ERR_INVALID;
+    for (int a = 0; a < p->ndim; a++) {
+        if (window_used) window_used[a] = (int32_t)p->hflags[1 + a];
+        if (max_abs_offset) max_abs_offset[a] = p->had_argmin ? (int32_t)p->hflags[4 + a] : -1;
+    }
+    if (p->hflags[0] & (kErrWindowCap | kErrWindowEdge)) return LO_ERR_WINDOW;
+    return LO_OK;
+}
+
+lo_status lo_kinetic_table(lo_plan_t p, int32_t axis, int64_t s0, int64_t count, double* out)
+{
+    if (!p || !out || axis < 0 || axis >= p->ndim || count < 0) return LO_ERR_INVALID;
+    for (int64_t i = 0; i < count; i++) {
+        const int64_t s = s0 + i;
+        out[i] = (s < -p->kcap[axis] || s > p->kcap[axis]) ? INFINITY : p->hkt[axis][s + p->kcap[axis]];
+    }
+    return LO_OK;
+}
+
+lo_status lo_effective_H(int32_t, const lo_desc*, const lo_potential*, double, double*, void*)
+{
+    return LO_ERR_UNSUPPORTED;
+}
+
+lo_status lo_backward(lo_plan_t, const double*, int64_t, int64_t, const double*, double*, double*, void*)
+{
+    return LO_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal declarations shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lo.h"
+
+namespace lo {
+
+constexpr int kMaxDim = 3;
+constexpr int kSlots = 3;          // rotating stats slots: read n%3, write (n+1)%3, clear (n+2)%3
+constexpr int kSlotWords = 10;     // per slot: [a] max fwd diff, [3+a] max -fwd diff, [6] max|w|,
+                                   // [7] max u, [8] max -u of the step result
+
+// error bits latched in flags[0]
+constexpr uint32_t kErrWindowCap = 1u;    // computed window exceeded the kinetic table
+constexpr uint32_t kErrWindowEdge = 2u;   // fixed window: argmin on the edge
+constexpr uint32_t kErrArgRange = 4u;     // argmin offset does not fit int16
+// flags layout: [0] error bits, [1+a] window used (max over steps), [4+a] max |argmin|
+constexpr int kFlagWords = 8;
+
+// Geometry of one axis sweep: a line is the set of points that differ only in
+// coordinate a.  Point (line l, position p) lives at
+//   inner(l) + stride * (p + n * outer(l)),  inner = l % stride, outer = l / stride.
+struct AxisGeom {
+    int64_t n;        // points on the line
+    int64_t stride;   // distance between consecutive points of a line
+    int64_t nlines;   // npts / n
+};
+
+// Kinetic cost table on the device: ktab[s] valid for s in [-kcap, kcap]
+// (pointer already offset to s = 0).
+struct KinTab {
+    const double* k;
+    int64_t kcap;
+};
+
+// Everything a sweep kernel needs besides the arrays.
+struct SweepArgs {
+    AxisGeom g;
+    KinTab kin;
+    int axis;
+    int ndim;
+    int32_t wfix;               // > 0: fixed window
+    double slack_extra;         // added to max|w| in the rounding slack of the window test
+    double dv_fwd;              // bound on tau*(V(x) - V(x+e_a)) over the grid and steps
+    double dv_bwd;              // bound on tau*(V(x+e_a) - V(x))
+    double osc_extra;           // growth of the oscillation through the sweeps before this one
+    const uint64_t* stats_in;   // slot read for this step (nullptr: row-local window)
+    uint64_t* stats_out;        // slot written (nullptr: none)
+    uint64_t* stats_clear;      // slot cleared by block 0 (nullptr: none)
+    uint32_t* flags;
+    const double* hv;           // tau*V at this step (nullptr: no potential step)
+    int16_t* argmin;            // nullptr or [npts] offsets for this axis
+    int halo;                   // LDS halo rows of the tile kernels
+    int tile_rows;              // targets per tile (tile kernels)
+    int kind;                   // kKindRow or kKindTile
+    int cap_is_error;           // 0 when the kinetic table is the cost's whole support
+};
+
+constexpr int kKindRow = 0;     // whole line in LDS, unit stride, window from the line itself
+constexpr int kKindTile = 1;    // tile of lines x targets with a halo, window from the stats slot
+
+// ---- kernel launchers (lo_kernels.hip) ----
+hipError_t launch_clear_slots(uint64_t* stats, hipStream_t s);
+hipError_t launch_stats(const double* u, int ndim, const int64_t* n, uint64_t* slot, hipStream_t s);
+hipError_t launch_synth_hv(const double* basis, const double* coef_dev, int nmodes, int64_t npts,
+                           double tau, double* hv, hipStream_t s);
+hipError_t launch_scale(const double* V, double tau, int64_t npts, double* hv, hipStream_t s);
+hipError_t launch_potential_diffs(const double* V, int ndim, const int64_t* n, double* out6,
+                                  hipStream_t s);
+hipError_t launch_sweep(int method, const double* in, double* out, const SweepArgs& a,
+                        hipStream_t s);
+
+// row kernel LDS capacity (doubles) -- lines longer than this use the tile kernel
+constexpr int64_t kRowLdsMax = 12288;
+
+}  // namespace lo

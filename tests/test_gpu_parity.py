@@ -1,0 +1,287 @@
+"""GPU path vs the FP64 oracle, through the C ABI.
+
+The brute-force path must equal the oracle bit for bit (values and int16
+argmin offsets); the fast path must agree within 1e-12 (max norm).  Inputs
+come from the seeded generators in paper_1210_4090_amd.workloads; no
+expected value comes from the GPU.
+"""
+import numpy as np
+import pytest
+
+from paper_1210_4090_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+FAST_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _gpu(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _plan(torch, n, tau, P, V=None, method="brute", **kw):
+    from paper_1210_4090_amd.lo import Plan
+    Vt = None if V is None else _gpu(torch, V)
+    p = Plan(n, tau, P, V=Vt, method=method, **kw)
+    p._Vhold = Vt
+    return p
+
+
+def _check(got, ref, method):
+    if method == "brute":
+        assert np.array_equal(got, ref), "max diff %g" % np.max(np.abs(got - ref))
+    else:
+        assert np.max(np.abs(got - ref)) <= FAST_TOL, np.max(np.abs(got - ref))
+
+
+def print_case(*a):
+    print("CASE", *a, flush=True)
+
+
+# ------------------------------------------------------------------ 1-D ----
+@pytest.mark.parametrize("method", ["brute", "fast"])
+def test_config1_full_run(torch_dev, orc, method):
+    """1-D torus N=256, P=0, V=cos 2pi x, u0=sin 2pi x, tau=0.05, 200 steps."""
+    torch = torch_dev
+    w = wl.config1()
+    print_case("config1", method)
+    ref = orc.run(w.u0, w.tau, w.P, w.steps, V=w.V)
+    p = _plan(torch, w.n, w.tau, w.P, w.V, method)
+    u = _gpu(torch, w.u0)
+    p.run(u, w.steps)
+    _check(u.cpu().numpy(), ref, method)
+
+
+@pytest.mark.parametrize("N,tau,P", [(5, 0.5, 0.35), (64, 0.05, 0.3), (257, 0.02, -0.7), (1000, 0.004, 1.3),
+                                     (3, 2.0, 0.9)])
+def test_1d_step_argmin_bitwise(torch_dev, orc, N, tau, P):
+    torch = torch_dev
+    print_case("1d step", N, tau, P)
+    u0 = wl.random_grid([N], 3 + N) + wl.smooth_grid([N], 4 + N)
+    V = wl.smooth_grid([N], 5 + N)
+    ref, refarg = orc.step(u0, tau, [P], V, with_argmin=True)
+    p = _plan(torch, [N], tau, [P], V)
+    u = _gpu(torch, u0)
+    arg = p.step(u, 0, argmin=True)
+    assert np.array_equal(u.cpu().numpy(), ref)
+    assert np.array_equal(arg.cpu().numpy().astype(np.int32), refarg)
+
+
+def test_1d_ties_lowest_offset(torch_dev, orc):
+    """Quantised data with many exact ties: the smallest offset wins on both sides."""
+    torch = torch_dev
+    N, tau, P = 48, 0.3, 0.0
+    u0 = np.round(wl.random_grid([N], 12) * 4) / 4
+    ref, refarg = orc.step(u0, tau, [P], None, with_argmin=True)
+    p = _plan(torch, [N], tau, [P])
+    u = _gpu(torch, u0)
+    arg = p.step(u, 0, argmin=True)
+    assert np.array_equal(u.cpu().numpy(), ref)
+    assert np.array_equal(arg.cpu().numpy().astype(np.int32), refarg)
+
+
+# ------------------------------------------------------------------ 2-D ----
+@pytest.mark.parametrize("method", ["brute", "fast"])
+@pytest.mark.parametrize("n", [(96, 80), (130, 257), (16, 300)])
+def test_2d_multistep(torch_dev, orc, method, n):
+    torch = torch_dev
+    print_case("2d multistep", n, method)
+    tau, P = 0.02, (0.3, -0.45)
+    u0 = wl.smooth_grid(list(n), 21, count=8, kmax=4)
+    V = wl.smooth_grid(list(n), 22)
+    ref = orc.run(u0, tau, P, 25, V=V)
+    p = _plan(torch, n, tau, P, V, method)
+    u = _gpu(torch, u0)
+    p.run(u, 25)
+    _check(u.cpu().numpy(), ref, method)
+
+
+def test_2d_step_argmin_bitwise(torch_dev, orc):
+    torch = torch_dev
+    n, tau, P = (70, 131), 0.03, (0.25, 0.6)
+    u0 = wl.random_grid(list(n), 31, 0.3) + wl.smooth_grid(list(n), 32)
+    V = wl.smooth_grid(list(n), 33)
+    ref, refarg = orc.step(u0, tau, P, V, with_argmin=True)
+    p = _plan(torch, n, tau, P, V)
+    u = _gpu(torch, u0)
+    arg = p.step(u, 0, argmin=True)
+    assert np.array_equal(u.cpu().numpy(), ref)
+    assert np.array_equal(arg.cpu().numpy().astype(np.int32), refarg)
+
+
+# ------------------------------------------------------------------ 3-D ----
+@pytest.mark.parametrize("method", ["brute", "fast"])
+def test_3d_multistep(torch_dev, orc, method):
+    torch = torch_dev
+    n, tau, P = (24, 20, 33), 0.05, (0.2, -0.1, 0.05)
+    print_case("3d multistep", method)
+    u0 = wl.smooth_grid(list(n), 41, count=10, kmax=3)
+    V = wl.smooth_grid(list(n), 42)
+    ref = orc.run(u0, tau, P, 12, V=V)
+    p = _plan(torch, n, tau, P, V, method)
+    u = _gpu(torch, u0)
+    p.run(u, 12)
+    _check(u.cpu().numpy(), ref, method)
+
+
+def test_3d_step_argmin_bitwise(torch_dev, orc):
+    torch = torch_dev
+    n, tau, P = (17, 40, 9), 0.04, (0.5, -0.2, 0.1)
+    u0 = wl.random_grid(list(n), 51, 0.2) + wl.smooth_grid(list(n), 52)
+    V = wl.smooth_grid(list(n), 53)
+    ref, refarg = orc.step(u0, tau, P, V, with_argmin=True)
+    p = _plan(torch, n, tau, P, V)
+    u = _gpu(torch, u0)
+    arg = p.step(u, 0, argmin=True)
+    assert np.array_equal(u.cpu().numpy(), ref)
+    assert np.array_equal(arg.cpu().numpy().astype(np.int32), refarg)
+
+
+# ------------------------------------------------------ other features ----
+def test_kinetic_table_matches_independent_evaluation(torch_dev, orc):
+    torch = torch_dev
+    p = _plan(torch, (64, 48), 0.03, (0.3, -1.2))
+    for a, (N, P) in enumerate([(64, 0.3), (48, -1.2)]):
+        s = np.arange(-90, 91)        # inside both tables (they span two periods)
+        assert np.array_equal(p.kinetic_table(a, -90, 181), orc.kinetic(s, 1.0 / N, 0.03, P))
+        far = p.kinetic_table(a, 10 * N, 3)
+        assert np.all(np.isinf(far))
+
+
+def test_time_dependent_potential(torch_dev, orc):
+    """V(t_n) = sum_m tcoef[n, m] phi_m (the paper's second experiment has this form)."""
+    torch = torch_dev
+    from paper_1210_4090_amd.lo import Plan
+    N, tau, P, steps = 200, 0.03, 1.0, 30
+    x = np.arange(N) / N
+    basis = np.stack([np.cos(4 * np.pi * x), np.sin(2 * np.pi * x)])
+    tcoef = np.stack([np.sin(tau * np.arange(steps)), 0.3 * np.cos(tau * np.arange(steps))], axis=1)
+    u0 = np.cos(2 * np.pi * x)
+    ref = orc.run(u0, tau, [P], steps, basis=basis, tcoef=tcoef)
+    B = _gpu(torch, basis)
+    p = Plan([N], tau, [P], basis=B, tcoef=tcoef, method="brute")
+    u = _gpu(torch, u0)
+    p.run(u, steps)
+    assert np.array_equal(u.cpu().numpy(), ref)
+
+
+def test_static_basis_potential(torch_dev, orc):
+    torch = torch_dev
+    from paper_1210_4090_amd.lo import Plan
+    n = (40, 36)
+    kv, kinds = wl.half_plane_basis(5)
+    basis = wl.basis_tables(list(n), kv, kinds)
+    coef = np.random.default_rng(3).standard_normal(basis.shape[0])
+    V = orc.potential(basis, coef)
+    u0 = wl.smooth_grid(list(n), 61)
+    ref = orc.run(u0, 0.04, [0.1, 0.2], 10, V=V)
+    B = _gpu(torch, basis)
+    p = Plan(n, 0.04, [0.1, 0.2], basis=B, coef=coef, method="brute")
+    u = _gpu(torch, u0)
+    p.run(u, 10)
+    assert np.array_equal(u.cpu().numpy(), ref)
+
+
+def test_user_convex_kinetic_table(torch_dev, orc):
+    """A general convex tau*K* (hypothesis (i)) given as a table."""
+    torch = torch_dev
+    N, tau = 90, 0.05
+    s = np.arange(-60, 61)
+    d = s / N
+    tab = tau * (0.5 * (d / tau) ** 2 + 0.1 * (d / tau) ** 4) - 0.2 * d
+    u0 = wl.smooth_grid([N], 71) + 0.1 * wl.random_grid([N], 72)
+    V = wl.smooth_grid([N], 73)
+    ref = u0.copy()
+    for k in range(6):
+        ref = orc.step(ref, tau, [0.0], V, ktabs=[tab])
+    p = _plan(torch, [N], tau, [0.0], V, kstar_tabs=[tab])
+    u = _gpu(torch, u0)
+    p.run(u, 6)
+    assert np.array_equal(u.cpu().numpy(), ref)
+
+
+def test_fixed_window_saturation_is_reported(torch_dev):
+    torch = torch_dev
+    from paper_1210_4090_amd._lib import LoError, LO_ERR_WINDOW
+    N = 128
+    u0 = wl.smooth_grid([N], 81) * 3
+    p = _plan(torch, [N], 0.05, [0.0], window=[2])
+    u = _gpu(torch, u0)
+    with pytest.raises(LoError) as ei:
+        p.run(u, 3)
+    assert ei.value.status == LO_ERR_WINDOW
+
+
+def test_auto_window_equals_wide_fixed_window(torch_dev):
+    """The rigorous device window and a generous fixed window agree bit for bit."""
+    torch = torch_dev
+    n = (64, 50)
+    u0 = wl.smooth_grid(list(n), 91, count=8, kmax=4)
+    V = wl.smooth_grid(list(n), 92)
+    a = _plan(torch, n, 0.03, (0.2, 0.4), V)
+    b = _plan(torch, n, 0.03, (0.2, 0.4), V, window=[60, 48])
+    ua, ub = _gpu(torch, u0), _gpu(torch, u0)
+    a.run(ua, 15)
+    b.run(ub, 15)
+    assert torch.equal(ua, ub)
+    w, _ = a.diag()
+    assert all(0 < x < 60 for x in w)
+
+
+def test_deterministic_repeat(torch_dev):
+    torch = torch_dev
+    w = wl.config2(n=256, steps=10)
+    outs = []
+    for _ in range(2):
+        p = _plan(torch, w.n, w.tau, w.P, w.V, "fast")
+        u = _gpu(torch, w.u0)
+        p.run(u, 40)
+        outs.append(u.clone())
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_resume_is_bitwise(torch_dev):
+    """Running 20 steps, or 8 then 12 from step 8, gives identical bits."""
+    torch = torch_dev
+    w = wl.config2(n=128, steps=20)
+    p = _plan(torch, w.n, w.tau, w.P, w.V, "brute")
+    u1 = _gpu(torch, w.u0)
+    p.run(u1, 20)
+    u2 = _gpu(torch, w.u0)
+    p.run(u2, 8, n0=0)
+    p.run(u2, 12, n0=8)
+    assert torch.equal(u1, u2)
+
+
+# ----------------------------------------------------------- full sizes ----
+@pytest.mark.parametrize("method", ["brute", "fast"])
+def test_config2_full_size_first_steps(torch_dev, orc, method):
+    """2048^2 at the benchmark's plan and launch configuration: 2 steps vs the
+    oracle on the whole grid."""
+    torch = torch_dev
+    w = wl.config2()
+    print_case("config2 full", method)
+    ref = orc.run(w.u0, w.tau, w.P, 2, V=w.V)
+    p = _plan(torch, w.n, w.tau, w.P, w.V, method)
+    u = _gpu(torch, w.u0)
+    p.run(u, 2)
+    _check(u.cpu().numpy(), ref, method)
+
+
+@pytest.mark.parametrize("method", ["brute", "fast"])
+def test_config3_full_size_first_steps(torch_dev, orc, method):
+    torch = torch_dev
+    w = wl.config3()
+    print_case("config3 full", method)
+    ref = orc.run(w.u0, w.tau, w.P, 2, V=w.V)
+    p = _plan(torch, w.n, w.tau, w.P, w.V, method)
+    u = _gpu(torch, w.u0)
+    p.run(u, 2)
+    _check(u.cpu().numpy(), ref, method)
