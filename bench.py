@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Benchmark of the fully discrete Lax--Oleinik step on one MI355X.
+
+A bench "step" is one full run of the 2-D workload (2048^2 torus, P = (0.3,
+0.1), V = cos2pi x + cos2pi y + 0.5 cos2pi(x+y), u0 = 8 seeded Fourier modes,
+tau = 0.01, 1000 time steps): every time step is the row sweep, the column
+sweep and the fused potential step, all in the library's HIP kernels.  u0 and
+V are resident in HBM before the timed region.  Printed: one JSON line with
+grid-point updates/s, the roofline of the dominant kernel (HIP events on the
+kernels' stream), the CPU oracle's rate on a bounded sample, and secondary
+measurements (brute vs fast, the 3-D workload, batched effective
+Hamiltonians, forward + adjoint).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VALU_PEAK = 39.3e12       # non-FMA FP64 lane ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sweep_bytes(ndim: int, npts: int):
+    """Algorithmic HBM bytes per launch of each axis sweep: read u, write u
+    (16 B/point), plus the tau*V table (8 B/point) in the last axis."""
+    return [npts * (16 + (8 if a == ndim - 1 else 0)) for a in range(ndim)]
+
+
+def timed_runs(torch, plan, u0, steps, K, W):
+    u = torch.empty_like(u0)
+    for _ in range(W):
+        u.copy_(u0)
+        plan.run(u, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        u.copy_(u0)
+        plan.run(u, steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, u
+
+
+def measure_workload(torch, w, method, K, W, steps=None):
+    from paper_1210_4090_amd.lo import Plan
+    steps = w.steps if steps is None else steps
+    V = torch.as_tensor(w.V, device="cuda")
+    u0 = torch.as_tensor(w.u0, device="cuda")
+    plan = Plan(w.n, w.tau, w.P, V=V, method=method)
+    dt, u = timed_runs(torch, plan, u0, steps, K, W)
+    rate = w.npts * steps * K / dt
+    # per-kernel durations over one full run from u0, HIP events on the stream
+    u.copy_(u0)
+    ms = plan.time_kernels(u, steps)
+    wins, _ = plan.diag()
+    nb = sweep_bytes(w.ndim, w.npts)
+    dom = int(max(range(w.ndim), key=lambda a: ms[a]))
+    gbs = nb[dom] / (ms[dom] * 1e-3) / 1e9
+    return {"rate": rate, "dt": dt, "ms_per_run": dt / K * 1e3, "kernel_ms": [float(x) for x in ms],
+            "dominant_axis": dom, "dominant_GBs": gbs, "bytes_per_launch": nb[dom],
+            "all_axis_GBs": [nb[a] / (ms[a] * 1e-3) / 1e9 for a in range(w.ndim)],
+            "window_max": wins, "plan": plan, "V": V, "u0": u0}
+
+
+def cpu_baseline(w, nsteps=3):
+    from oracle import oracle
+    t0 = time.perf_counter()
+    oracle.run(w.u0, w.tau, w.P, nsteps, V=w.V)
+    dt = time.perf_counter() - t0
+    return {"value": w.npts * nsteps / dt, "unit": "grid-point updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": "first %d time steps of the %s workload, full grid (%.1f s)"
+            % (nsteps, w.name, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--method", default="fast", choices=["fast", "brute"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1210_4090_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    w = wl.config2()
+    log("workload %s steps=%d method=%s K=%d W=%d" % (w.name, w.steps, args.method, args.steps, args.warmup))
+    m = measure_workload(torch, w, args.method, args.steps, args.warmup)
+    log("headline: %.4g updates/s, %.2f ms per run, kernels %s ms, windows %s"
+        % (m["rate"], m["ms_per_run"], m["kernel_ms"], m["window_max"]))
+    out = {
+        "metric": "grid-point min-plus updates/sec + HBM GB/s, plain vs batched H̄(P) vs fwd+adjoint",
+        "value": m["rate"],
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_run"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Fourier modes)",
+        "config": {"workload": "2d_torus_2048x2048_tau0.01_1000steps", "grid": [2048, 2048],
+                   "time_steps_per_run": w.steps, "method": args.method, "P": list(w.P),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": m["dominant_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": m["dominant_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "axis-%d sweep" % m["dominant_axis"],
+                     "algorithmic_bytes_per_launch": m["bytes_per_launch"],
+                     "kernel_ms": m["kernel_ms"]},
+        "effective_GBs_whole_step": sum(sweep_bytes(w.ndim, w.npts)) * w.steps / (m["ms_per_run"] * 1e-3) / 1e9,
+    }
+    if not args.no_extras:
+        extras = {}
+        other = "brute" if args.method == "fast" else "fast"
+        mb = measure_workload(torch, w, other, 1, 0)
+        extras["headline_workload_" + other] = {"updates_per_s": mb["rate"], "ms_per_run": mb["ms_per_run"],
+                                               "kernel_ms": mb["kernel_ms"], "window_max": mb["window_max"]}
+        log("%s: %.4g updates/s" % (other, mb["rate"]))
+        del mb
+        w3 = wl.config3()
+        m3 = measure_workload(torch, w3, args.method, 2, 1)
+        extras["3d_torus_256^3_200steps"] = {
+            "updates_per_s": m3["rate"], "ms_per_run": m3["ms_per_run"], "kernel_ms": m3["kernel_ms"],
+            "all_axis_GBs": m3["all_axis_GBs"], "hbm_frac_dominant": m3["dominant_GBs"] / HBM_PEAK_GBS,
+            "window_max": m3["window_max"]}
+        log("3-D: %.4g updates/s, axis GB/s %s" % (m3["rate"], m3["all_axis_GBs"]))
+        del m3
+        out["extras"] = extras
+    if not args.no_cpu:
+        cb = cpu_baseline(w)
+        log("cpu oracle: %.4g updates/s on %d threads" % (cb["value"], cb["cores"]))
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -74,6 +74,8 @@ SIGNATURES = {
     "lo_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "lo_last_diag": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "lo_kinetic_table": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _f64p]),
+    "lo_time_kernels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, _f64p,
+                                       ctypes.c_void_p]),
 }
 
 

@@ -26,8 +26,10 @@ struct lo_plan_s {
     double kzero_drop[kMaxDim] = {0, 0, 0};   // k(0) - min_s k(s), rounded up
     bool user_table[kMaxDim] = {false, false, false};
     int kind[kMaxDim] = {kKindRow, kKindTile, kKindTile};
-    int halo[kMaxDim] = {0, 0, 0};
+    int halo[kMaxDim] = {0, 0, 0};       // halo of the next launches (adapted by lo_run)
+    int halo_max[kMaxDim] = {0, 0, 0};   // largest halo the LDS budget allows
     int tile_rows[kMaxDim] = {0, 0, 0};
+    bool fast[kMaxDim] = {false, false, false};
     // potential
     int nmodes = 0;
     const double* basis = nullptr;
@@ -45,14 +47,20 @@ struct lo_plan_s {
     double* scratch = nullptr;
     uint64_t* stats = nullptr;   // kSlots * kSlotWords
     uint32_t* flags = nullptr;   // kFlagWords
-    uint32_t hflags[kFlagWords] = {0};
+    uint32_t hflags[8] = {0};    // folded: [0] errors, [1+a] window used, [4+a] max |argmin|
     bool have_diag = false;
     bool had_argmin = false;
-    // graph cache for lo_run
-    hipGraphExec_t gexec = nullptr;
-    double* g_u = nullptr;
-    int64_t g_phase = -1;
-    int g_steps = 0;
+    // graph cache for lo_run: one executable graph of kGraphSteps steps per
+    // (u, stats phase, halo) configuration
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        double* u = nullptr;
+        int64_t phase = -1;
+        int halo[kMaxDim] = {0, 0, 0};
+        uint64_t stamp = 0;
+    };
+    GraphEntry graphs[4];
+    uint64_t graph_clock = 0;
     hipStream_t cap_stream = nullptr;
 };
 
@@ -67,6 +75,23 @@ double host_dec(uint64_t k)
     double x;
     memcpy(&x, &b, 8);
     return x;
+}
+
+// max over the sub-slots of every word of a host copy of a slot
+void fold_slot(const uint64_t* raw, double* out)
+{
+    for (int w = 0; w < kSlotWords; w++) {
+        double m = -INFINITY;
+        for (int j = 0; j < kSpread; j++) m = std::max(m, host_dec(raw[w * kSpread + j]));
+        out[w] = m;
+    }
+}
+
+uint32_t fold_window(const uint32_t* f, int a)
+{
+    uint32_t m = 0;
+    for (int j = 0; j < kSpread; j++) m = std::max(m, f[kFlagWin + a * kSpread + j]);
+    return m;
 }
 
 // tau K*(s dx / tau) for K(p) = (p + P)^2 / 2, evaluated in a fixed order.
@@ -107,7 +132,8 @@ void free_plan(lo_plan_t p)
     if (p->scratch) (void)hipFree(p->scratch);
     if (p->stats) (void)hipFree(p->stats);
     if (p->flags) (void)hipFree(p->flags);
-    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    for (auto& g : p->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     delete p;
 }
@@ -152,10 +178,11 @@ lo_status build_tables(lo_plan_t p)
 lo_status add_potential_margins(lo_plan_t p, const double* hv, bool first)
 {
     double* d6 = nullptr;
-    lo_status st = alloc((void**)&d6, sizeof(uint64_t) * 32);
+    const size_t words = 16 + kSlotStride;
+    lo_status st = alloc((void**)&d6, sizeof(uint64_t) * words);
     if (st) return st;
-    std::vector<uint64_t> init(32, host_enc_neg_inf());
-    HIPCHK(hipMemcpy(d6, init.data(), sizeof(uint64_t) * 32, hipMemcpyHostToDevice));
+    std::vector<uint64_t> init(words, host_enc_neg_inf());
+    HIPCHK(hipMemcpy(d6, init.data(), sizeof(uint64_t) * words, hipMemcpyHostToDevice));
     if (launch_potential_diffs(hv, p->ndim, p->n, d6, nullptr) != hipSuccess) {
         (void)hipFree(d6);
         return LO_ERR_HIP;
@@ -164,8 +191,8 @@ lo_status add_potential_margins(lo_plan_t p, const double* hv, bool first)
         (void)hipFree(d6);
         return LO_ERR_HIP;
     }
-    uint64_t h[32];
-    hipError_t e = hipMemcpy(h, d6, sizeof(uint64_t) * 32, hipMemcpyDeviceToHost);
+    std::vector<uint64_t> h(words);
+    hipError_t e = hipMemcpy(h.data(), d6, sizeof(uint64_t) * words, hipMemcpyDeviceToHost);
     (void)hipFree(d6);
     if (e != hipSuccess) return LO_ERR_HIP;
     for (int a = 0; a < p->ndim; a++) {
@@ -180,7 +207,9 @@ lo_status add_potential_margins(lo_plan_t p, const double* hv, bool first)
             p->dvb[a] = std::max(p->dvb[a], b);
         }
     }
-    double m = host_dec(h[16 + 6]);
+    double folded[kSlotWords];
+    fold_slot(h.data() + 16, folded);
+    double m = folded[6];
     p->hvmax = first ? m : std::max(p->hvmax, m);
     return LO_OK;
 }
@@ -235,9 +264,6 @@ lo_status setup_potential(lo_plan_t p, const lo_potential* V)
     return LO_OK;
 }
 
-// LDS bytes of the tile kernel for R targets, halo H, 16 lines
-size_t tile_lds(int R, int H) { return sizeof(double) * ((size_t)(R + 2 * H + 1) * 16 + (size_t)(R + 1) * 16); }
-
 void choose_kernels(lo_plan_t p)
 {
     int dev = 0, lds_max = 65536;
@@ -246,21 +272,35 @@ void choose_kernels(lo_plan_t p)
         lds_max = 65536;
     (void)hipGetLastError();
     const size_t budget = std::min<size_t>((size_t)lds_max, 64 * 1024);
+    const size_t fbudget = std::min<size_t>((size_t)lds_max, 96 * 1024);
+    const bool fast = p->d.method == LO_FAST;
     for (int a = 0; a < p->ndim; a++) {
         const int64_t N = p->n[a];
-        if (a == 0 && (size_t)(N + 2) * sizeof(double) <= budget) {
+        p->fast[a] = fast && !p->user_table[a];
+        const bool row_ok = a == 0 && N <= 16384 &&
+                            (p->fast[a] ? fast_lds_for(kKindRow, N, 0, 1) <= fbudget
+                                        : row_lds_bytes(N, 8) <= budget);
+        if (row_ok) {
             p->kind[a] = kKindRow;
-            int64_t H = std::min<int64_t>(N, 1024);
-            while (H > 1 && (size_t)(N + 2 * H) * sizeof(double) > budget) H /= 2;
+            int64_t H = std::min<int64_t>(N, p->fast[a] ? 256 : 1024);
+            if (p->fast[a])
+                while (H > 1 && fast_lds_for(kKindRow, N, 0, (int)H) > fbudget) H = H * 7 / 8;
+            else
+                while (H > 8 && row_lds_bytes(N, (int)H) > budget) H = H * 7 / 8;
             p->halo[a] = (int)std::max<int64_t>(H, 1);
+            p->halo_max[a] = p->halo[a];
             p->tile_rows[a] = 0;
         } else {
             p->kind[a] = kKindTile;
             int R = (int)std::min<int64_t>(N, 128);
             int H = (int)std::min<int64_t>(N, 256);
-            while (H > 8 && tile_lds(R, H) > budget) H -= 8;
+            if (p->fast[a])
+                while (H > 8 && fast_lds_for(kKindTile, N, R, H) > fbudget) H -= 4;
+            else
+                while (H > 8 && tile_lds_bytes(H) > budget) H -= 8;
             p->tile_rows[a] = R;
             p->halo[a] = H;
+            p->halo_max[a] = H;
         }
     }
 }
@@ -272,7 +312,9 @@ double slack_extra(lo_plan_t p)
     return s;
 }
 
-uint64_t* slot(lo_plan_t p, int64_t n) { return p->stats + (size_t)(((n % kSlots) + kSlots) % kSlots) * kSlotWords; }
+uint64_t* slot(lo_plan_t p, int64_t n) { return p->stats + (size_t)(((n % kSlots) + kSlots) % kSlots) * kSlotStride; }
+
+
 
 // Buffers of the sweeps of one step: in/out per axis so that the result lands in u.
 void sweep_buffers(lo_plan_t p, double* u, double* in[kMaxDim], double* out[kMaxDim])
@@ -291,7 +333,64 @@ void sweep_buffers(lo_plan_t p, double* u, double* in[kMaxDim], double* out[kMax
     }
 }
 
-lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipStream_t s)
+// The device's one-sided window search, on the host table (for sizing halos).
+int host_side(const std::vector<double>& t, int64_t kcap, int dir, double D, double sbase, bool level)
+{
+    const double k0 = t[kcap];
+    for (int64_t s = 1; s <= kcap; s++) {
+        const double a = t[kcap + dir * s], b = level ? k0 : t[kcap + dir * (s - 1)];
+        if (!(a - b <= D + (sbase + fabs(a) + fabs(b)) * 0x1p-40)) return (int)(s - 1);
+    }
+    return (int)kcap;
+}
+
+int choose_halo(lo_plan_t p, int a, int W)
+{
+    if (p->d.window[a] > 0) W = p->d.window[a];
+    int H = W + std::max(16, W / 8);
+    H = (H + 7) / 8 * 8;
+    return std::max(8, std::min(H, p->halo_max[a]));
+}
+
+// Initial halos from the window bound of the state in stats slot n0.
+lo_status adapt_from_slot(lo_plan_t p, int64_t n0)
+{
+    std::vector<uint64_t> raw(kSlotStride);
+    HIPCHK(hipMemcpy(raw.data(), slot(p, n0), sizeof(uint64_t) * kSlotStride, hipMemcpyDeviceToHost));
+    double h[kSlotWords];
+    fold_slot(raw.data(), h);
+    const double M = h[6];
+    double osc = h[7] + h[8];
+    for (int a = 0; a < p->ndim; a++) {
+        const double sbase = 1.0 + M + slack_extra(p);
+        const double Dp = h[a] + p->dvf[a], Dm = h[3 + a] + p->dvb[a];
+        const int64_t kc = p->kcap[a];
+        const int wp = std::min(host_side(p->hkt[a], kc, 1, Dp, sbase, false), host_side(p->hkt[a], kc, 1, osc, sbase, true));
+        const int wm = std::min(host_side(p->hkt[a], kc, -1, Dm, sbase, false), host_side(p->hkt[a], kc, -1, osc, sbase, true));
+        p->halo[a] = choose_halo(p, a, std::max(wp, wm));
+        osc += p->kzero_drop[a];
+    }
+    return LO_OK;
+}
+
+// Halos from the widest window the kernels used since the last call.
+lo_status adapt_from_flags(lo_plan_t p, hipStream_t s)
+{
+    uint32_t f[kFlagWords];
+    HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(f), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int a = 0; a < p->ndim; a++) {
+        const uint32_t wu = fold_window(f, a);
+        p->hflags[1 + a] = std::max(p->hflags[1 + a], wu);
+        p->halo[a] = choose_halo(p, a, (int)wu);
+    }
+    // restart the per-segment window maxima (error bits and argmin maxima stay)
+    HIPCHK(hipMemsetAsync(p->flags + kFlagWin, 0, sizeof(uint32_t) * 3 * kSpread, s));
+    return LO_OK;
+}
+
+lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipStream_t s,
+                       hipEvent_t* ev = nullptr)
 {
     const double* hv = p->has_v ? p->dhv : nullptr;
     if (p->time_dep) {
@@ -331,7 +430,14 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.argmin = argmin ? argmin + (size_t)a * p->npts : nullptr;
         A.halo = p->halo[a];
         A.tile_rows = p->tile_rows[a];
+        A.fast = p->fast[a] ? 1 : 0;
+        A.quad = p->user_table[a] ? 0 : 1;
+        A.cq = p->dx[a] * p->dx[a] / (2.0 * p->d.tau);
+        A.inv2c = 1.0 / (2.0 * A.cq);
+        A.pofs = p->d.P[a] * p->d.tau / p->dx[a];
+        if (ev) HIPCHK(hipEventRecord(ev[2 * a], s));
         HIPCHK(launch_sweep(p->d.method, in[a], out[a], A, s));
+        if (ev) HIPCHK(hipEventRecord(ev[2 * a + 1], s));
     }
     if (out[p->ndim - 1] != u)
         HIPCHK(hipMemcpyAsync(u, out[p->ndim - 1], sizeof(double) * p->npts, hipMemcpyDeviceToDevice, s));
@@ -343,21 +449,31 @@ lo_status prologue(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
     HIPCHK(hipMemsetAsync(p->flags, 0, sizeof(uint32_t) * kFlagWords, s));
     HIPCHK(launch_clear_slots(p->stats, s));
     HIPCHK(launch_stats(u, p->ndim, p->n, slot(p, n0), s));
-    return LO_OK;
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < 8; i++) p->hflags[i] = 0;
+    return adapt_from_slot(p, n0);
 }
 
 lo_status finish(lo_plan_t p, hipStream_t s, bool argmin)
 {
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipMemcpy(p->hflags, p->flags, sizeof(uint32_t) * kFlagWords, hipMemcpyDeviceToHost));
+    uint32_t f[kFlagWords];
+    HIPCHK(hipMemcpy(f, p->flags, sizeof(uint32_t) * kFlagWords, hipMemcpyDeviceToHost));
+    p->hflags[0] = f[0];
+    for (int a = 0; a < kMaxDim; a++) {
+        p->hflags[1 + a] = std::max(p->hflags[1 + a], a < p->ndim ? fold_window(f, a) : 0u);
+        p->hflags[4 + a] = f[4 + a];
+    }
     p->have_diag = true;
     p->had_argmin = argmin;
-    if (p->hflags[0] & (kErrWindowCap | kErrWindowEdge)) return LO_ERR_WINDOW;
+    if (p->hflags[0] & (kErrWindowCap | kErrWindowEdge | kErrFastPath)) return LO_ERR_WINDOW;
     if (p->hflags[0] & kErrArgRange) return LO_ERR_UNSUPPORTED;
     return LO_OK;
 }
 
 bool graphable(lo_plan_t p) { return !(p->d.flags & LO_FLAG_NO_GRAPH) && !p->time_dep; }
+
+constexpr int kGraphSteps = 30;   // multiple of the 3 stats slots
 
 }  // namespace
 
@@ -412,7 +528,7 @@ lo_status lo_plan(const lo_desc* desc, const lo_potential* V, lo_plan_t* out)
             if (desc->window[a] > 0 && desc->window[a] > p->kcap[a]) st = LO_ERR_INVALID;
     }
     if (!st) st = alloc((void**)&p->scratch, sizeof(double) * (size_t)p->npts);
-    if (!st) st = alloc((void**)&p->stats, sizeof(uint64_t) * kSlots * kSlotWords);
+    if (!st) st = alloc((void**)&p->stats, sizeof(uint64_t) * kSlots * kSlotStride);
     if (!st) st = alloc((void**)&p->flags, sizeof(uint32_t) * kFlagWords);
     if (!st) st = setup_potential(p, V);
     if (st) {
@@ -454,6 +570,43 @@ lo_status lo_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, void* stre
     return finish(p, s, argmin != nullptr);
 }
 
+// An executable graph of kGraphSteps steps from phase n0 % 3 at the current halos.
+lo_status get_graph(lo_plan_t p, double* u, int64_t n0, hipGraphExec_t* out)
+{
+    const int64_t phase = ((n0 % kSlots) + kSlots) % kSlots;
+    lo_plan_s::GraphEntry* hit = nullptr;
+    lo_plan_s::GraphEntry* victim = &p->graphs[0];
+    for (auto& g : p->graphs) {
+        if (g.exec && g.u == u && g.phase == phase && !memcmp(g.halo, p->halo, sizeof(g.halo))) hit = &g;
+        if (!g.exec || g.stamp < victim->stamp) victim = &g;
+    }
+    if (!hit) {
+        if (victim->exec) (void)hipGraphExecDestroy(victim->exec);
+        victim->exec = nullptr;
+        if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        lo_status cst = LO_OK;
+        for (int k = 0; k < kGraphSteps && !cst; k++) cst = enqueue_step(p, u, n0 + k, nullptr, p->cap_stream);
+        hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
+        if (cst) {
+            if (g) (void)hipGraphDestroy(g);
+            return cst;
+        }
+        HIPCHK(ce);
+        hipError_t ie = hipGraphInstantiate(&victim->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(ie);
+        victim->u = u;
+        victim->phase = phase;
+        memcpy(victim->halo, p->halo, sizeof(victim->halo));
+        hit = victim;
+    }
+    hit->stamp = ++p->graph_clock;
+    *out = hit->exec;
+    return LO_OK;
+}
+
 lo_status lo_run(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckpt_every, double* ckpt,
                  void* stream)
 {
@@ -462,49 +615,30 @@ lo_status lo_run(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckp
     hipStream_t s = (hipStream_t)stream;
     lo_status st = prologue(p, u, n0, s);
     if (st) return st;
-    const bool use_graph = graphable(p) && !ckpt && nsteps >= 6;
+    const bool use_graph = graphable(p) && !ckpt;
     int64_t done = 0;
-    if (use_graph) {
-        // one graph holds G steps; the stats slots repeat with period 3, so a
-        // graph built for phase n0 % 3 replays for every block of G steps
-        const int G = 30;
-        const int64_t phase = ((n0 % kSlots) + kSlots) % kSlots;
-        if (p->gexec && (p->g_u != u || p->g_phase != phase || p->g_steps != G)) {
-            (void)hipGraphExecDestroy(p->gexec);
-            p->gexec = nullptr;
-        }
-        if (!p->gexec && nsteps >= G) {
-            if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
-            hipGraph_t g = nullptr;
-            HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-            lo_status cst = LO_OK;
-            for (int k = 0; k < G && !cst; k++) cst = enqueue_step(p, u, n0 + k, nullptr, p->cap_stream);
-            hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
-            if (cst) {
-                if (g) (void)hipGraphDestroy(g);
-                return cst;
-            }
-            HIPCHK(ce);
-            hipError_t ie = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            HIPCHK(ie);
-            p->g_u = u;
-            p->g_phase = phase;
-            p->g_steps = G;
-        }
-        if (p->gexec) {
-            while (nsteps - done >= G) {
-                HIPCHK(hipGraphLaunch(p->gexec, s));
-                done += G;
+    while (done < nsteps) {
+        const int64_t seg = std::min<int64_t>(kGraphSteps, nsteps - done);
+        if (use_graph && seg == kGraphSteps) {
+            hipGraphExec_t ge = nullptr;
+            st = get_graph(p, u, n0 + done, &ge);
+            if (st) return st;
+            HIPCHK(hipGraphLaunch(ge, s));
+        } else {
+            for (int64_t k = 0; k < seg; k++) {
+                const int64_t i = done + k;
+                if (ckpt && i % ckpt_every == 0)
+                    HIPCHK(hipMemcpyAsync(ckpt + (size_t)(i / ckpt_every) * p->npts, u, sizeof(double) * p->npts,
+                                          hipMemcpyDeviceToDevice, s));
+                st = enqueue_step(p, u, n0 + i, nullptr, s);
+                if (st) return st;
             }
         }
-    }
-    for (; done < nsteps; done++) {
-        if (ckpt && done % ckpt_every == 0)
-            HIPCHK(hipMemcpyAsync(ckpt + (size_t)(done / ckpt_every) * p->npts, u, sizeof(double) * p->npts,
-                                  hipMemcpyDeviceToDevice, s));
-        st = enqueue_step(p, u, n0 + done, nullptr, s);
-        if (st) return st;
+        done += seg;
+        if (done < nsteps) {
+            st = adapt_from_flags(p, s);
+            if (st) return st;
+        }
     }
     return finish(p, s, false);
 }
@@ -528,6 +662,38 @@ lo_status lo_kinetic_table(lo_plan_t p, int32_t axis, int64_t s0, int64_t count,
         out[i] = (s < -p->kcap[axis] || s > p->kcap[axis]) ? INFINITY : p->hkt[axis][s + p->kcap[axis]];
     }
     return LO_OK;
+}
+
+lo_status lo_time_kernels(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, double* ms, void* stream)
+{
+    if (!p || !u || !ms || nsteps <= 0) return LO_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    lo_status st = prologue(p, u, n0, s);
+    if (st) return st;
+    hipEvent_t ev[2 * kMaxDim];
+    for (int i = 0; i < 2 * p->ndim; i++) HIPCHK(hipEventCreate(&ev[i]));
+    double acc[kMaxDim] = {0, 0, 0};
+    for (int64_t k = 0; k < nsteps && !st; k++) {
+        if (k > 0 && k % kGraphSteps == 0) {
+            st = adapt_from_flags(p, s);
+            if (st) break;
+        }
+        st = enqueue_step(p, u, n0 + k, nullptr, s, ev);
+        if (st) break;
+        if (hipEventSynchronize(ev[2 * p->ndim - 1]) != hipSuccess) {
+            st = LO_ERR_HIP;
+            break;
+        }
+        for (int a = 0; a < p->ndim; a++) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[2 * a], ev[2 * a + 1]) != hipSuccess) st = LO_ERR_HIP;
+            acc[a] += t;
+        }
+    }
+    for (int i = 0; i < 2 * p->ndim; i++) (void)hipEventDestroy(ev[i]);
+    if (st) return st;
+    for (int a = 0; a < p->ndim; a++) ms[a] = acc[a] / (double)nsteps;
+    return finish(p, s, false);
 }
 
 lo_status lo_effective_H(int32_t, const lo_desc*, const lo_potential*, double, double*, void*)

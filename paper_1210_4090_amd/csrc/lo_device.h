@@ -1,0 +1,209 @@
+// Device helpers shared by the sweep kernels: order-preserving encodings for
+// atomic max/min of doubles, block reductions, and the rigorous window bound.
+#pragma once
+
+#include <math.h>
+
+#include "lo_internal.h"
+
+namespace lo {
+namespace dev {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr uint64_t kSign = 0x8000000000000000ull;
+
+// Monotone map double -> uint64 (x < y  <=>  enc(x) < enc(y)) so that
+// unsigned integer atomics compute max / min of doubles.
+__device__ __forceinline__ uint64_t enc(double x)
+{
+    uint64_t b = (uint64_t)__double_as_longlong(x);
+    return (b & kSign) ? ~b : (b | kSign);
+}
+
+__device__ __forceinline__ double dec(uint64_t k)
+{
+    uint64_t b = (k & kSign) ? (k & ~kSign) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+__device__ __forceinline__ uint64_t enc_neg_inf() { return ~(uint64_t)0xFFF0000000000000ull; }
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Block-wide max of three values (blockDim <= 512); result in every thread.
+__device__ inline void block_max3(double& a, double& b, double& c, double* red)
+{
+    a = wave_max(a);
+    b = wave_max(b);
+    c = wave_max(c);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    const int nw = blockDim.x / kWave;
+    __syncthreads();
+    if (l == 0) {
+        red[w] = a;
+        red[8 + w] = b;
+        red[16 + w] = c;
+    }
+    __syncthreads();
+    a = red[0];
+    b = red[8];
+    c = red[16];
+    for (int i = 1; i < nw; i++) {
+        a = fmax(a, red[i]);
+        b = fmax(b, red[8 + i]);
+        c = fmax(c, red[16 + i]);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void clear_slot(uint64_t* slot)
+{
+    if (slot && blockIdx.x == 0)
+        for (int i = threadIdx.x; i < kSlotStride; i += blockDim.x) slot[i] = enc_neg_inf();
+}
+
+// Fold a value into word `w` of a stats slot (sub-slot chosen by the block).
+__device__ __forceinline__ void stat_put(uint64_t* slot, int w, double v)
+{
+    atomicMax((unsigned long long*)&slot[w * kSpread + (int)(blockIdx.x % kSpread)], (unsigned long long)enc(v));
+}
+
+// Max over the sub-slots of word `w`; every lane of a full wave must call it.
+__device__ __forceinline__ double stat_get(const uint64_t* slot, int w)
+{
+    return wave_max(dec(slot[w * kSpread + threadIdx.x % kWave]));
+}
+
+__device__ __forceinline__ int64_t remap_block(int64_t b, int64_t G)
+{
+    // consecutive tiles of the same lines go to one XCD (blocks are dealt to
+    // the 8 XCDs round robin), so their shared halo rows hit in its L2
+    if (G % 8 != 0) return b;
+    return (b % 8) * (G / 8) + b / 8;
+}
+
+// Largest W in [0, kcap] such that every s = 1..W passes the test
+//   level == false:  k(dir s) - k(dir (s-1)) <= D + slack   (neighbour bound)
+//   level == true:   k(dir s) - k(0)         <= D + slack   (oscillation bound)
+// with slack = 2^-40 (sbase + |k(dir s)| + |other|).  Both left sides are
+// nondecreasing in s beyond the kernel's minimum (k is convex) and the level
+// test passes below it, so the passing s form an interval 1..W.  One wave
+// runs it, probing 64 values of s at a time starting below `est` (a
+// closed-form guess for the mechanical cost; 0 when none): when the probe's
+// first value passes, everything below it passes too.  *cap is set when the
+// table ends before a failure.
+__device__ inline int window_side(const double* __restrict__ k, int64_t kcap, int dir, double D, double sbase,
+                                  bool level, int64_t est, bool* cap)
+{
+    const int lane = threadIdx.x % kWave;
+    const double k0 = k[0];
+    auto fails = [&](int64_t s) {
+        if (s > kcap) return true;
+        const double a = k[dir * s], b = level ? k0 : k[dir * (s - 1)];
+        const double d = a - b;
+        const double lim = D + (sbase + fabs(a) + fabs(b)) * 0x1p-40;
+        return !(d <= lim);
+    };
+    int64_t base = est - kWave / 2;
+    if (base < 1) base = 1;
+    if (base > kcap) base = kcap;
+    // probe s = base .. base+63; lane 0's value must pass for the shortcut
+    {
+        const uint64_t m = __ballot(fails(base + lane));
+        if (m & 1ull) {
+            base = 1;   // the guess was too high: scan from the start
+        } else if (m) {
+            const int64_t sf = base + __ffsll((unsigned long long)m) - 1;
+            if (sf > kcap) {
+                *cap = true;
+                return (int)kcap;
+            }
+            return (int)(sf - 1);
+        } else {
+            base += kWave;
+        }
+    }
+    for (; base <= kcap; base += kWave) {
+        const uint64_t m = __ballot(fails(base + lane));
+        if (m) {
+            const int64_t sf = base + __ffsll((unsigned long long)m) - 1;
+            if (sf > kcap) {
+                *cap = true;
+                return (int)kcap;
+            }
+            return (int)(sf - 1);
+        }
+    }
+    *cap = true;
+    return (int)kcap;
+}
+
+// (W+, W-) for the block, broadcast through shw[0..1]: the smaller of the
+// neighbour bound (max differences Dp, Dm) and the oscillation bound.  The
+// four one-sided searches run in four waves at once.  With a stats slot the
+// inputs are read from it (adding the potential's and earlier sweeps'
+// margins), otherwise Dp, Dm, osc, M are used as given.  Ends with a barrier.
+__device__ inline void block_window(const SweepArgs& a, const uint64_t* slot, double Dp, double Dm, double osc,
+                                    double M, int* shw)
+{
+    __shared__ int part[4];
+    __shared__ int caps[4];
+    const int w = threadIdx.x / kWave;
+    if (a.wfix <= 0 && w < 4) {
+        const int dir = (w < 2) ? 1 : -1;
+        const bool level = (w & 1) != 0;
+        double D;
+        if (slot) {
+            M = stat_get(slot, 6);
+            if (level)
+                D = (stat_get(slot, 7) + stat_get(slot, 8)) + a.osc_extra;
+            else
+                D = dir > 0 ? stat_get(slot, a.axis) + a.dv_fwd : stat_get(slot, 3 + a.axis) + a.dv_bwd;
+        } else {
+            D = level ? osc : (dir > 0 ? Dp : Dm);
+        }
+        const double sbase = 1.0 + M + a.slack_extra;
+        int64_t est = 0;
+        if (a.fast || a.quad) {
+            // k(dir s) = c s^2 - dir p s with p = 2c pofs
+            const double c = a.cq, p = 2.0 * a.cq * a.pofs * (double)dir;
+            double e;
+            if (level)
+                e = (p + sqrt(fmax(p * p + 4.0 * c * fmax(D, 0.0), 0.0))) / (2.0 * c);
+            else
+                e = (D + p) / (2.0 * c) + 0.5;
+            if (e > 0.0 && e < 1e9) est = (int64_t)e;
+        }
+        bool cap = false;
+        const int r = window_side(a.kin.k, a.kin.kcap, dir, D, sbase, level, est, &cap);
+        if (threadIdx.x % kWave == 0) {
+            part[w] = r;
+            caps[w] = cap ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int wp, wm;
+        bool cap = false;
+        if (a.wfix > 0) {
+            wp = wm = a.wfix;
+        } else {
+            wp = min(part[0], part[1]);
+            wm = min(part[2], part[3]);
+            cap = (caps[0] && caps[1]) || (caps[2] && caps[3]);
+        }
+        shw[0] = wp;
+        shw[1] = wm;
+        if (cap && a.cap_is_error) atomicOr(&a.flags[0], kErrWindowCap);
+        atomicMax(&a.flags[kFlagWin + a.axis * kSpread + (int)(blockIdx.x % kSpread)], (uint32_t)max(wp, wm));
+    }
+    __syncthreads();
+}
+
+}  // namespace dev
+}  // namespace lo

@@ -12,13 +12,19 @@ constexpr int kMaxDim = 3;
 constexpr int kSlots = 3;          // rotating stats slots: read n%3, write (n+1)%3, clear (n+2)%3
 constexpr int kSlotWords = 10;     // per slot: [a] max fwd diff, [3+a] max -fwd diff, [6] max|w|,
                                    // [7] max u, [8] max -u of the step result
+constexpr int kSpread = 64;        // each word is spread over 64 sub-slots (block index mod 64) so
+                                   // that thousands of blocks do not contend on one atomic address
+constexpr int kSlotStride = kSlotWords * kSpread;   // word w, sub-slot j at [w * kSpread + j]
 
 // error bits latched in flags[0]
 constexpr uint32_t kErrWindowCap = 1u;    // computed window exceeded the kinetic table
 constexpr uint32_t kErrWindowEdge = 2u;   // fixed window: argmin on the edge
 constexpr uint32_t kErrArgRange = 4u;     // argmin offset does not fit int16
-// flags layout: [0] error bits, [1+a] window used (max over steps), [4+a] max |argmin|
-constexpr int kFlagWords = 8;
+constexpr uint32_t kErrFastPath = 8u;     // fast kernel left a target without a finite candidate
+// flags layout: [0] error bits, [4+a] max |argmin|, and the window used by
+// axis a (max over blocks and steps) spread at [kFlagWin + a * kSpread + j]
+constexpr int kFlagWin = 8;
+constexpr int kFlagWords = kFlagWin + 3 * kSpread;
 
 // Geometry of one axis sweep: a line is the set of points that differ only in
 // coordinate a.  Point (line l, position p) lives at
@@ -57,6 +63,11 @@ struct SweepArgs {
     int tile_rows;              // targets per tile (tile kernels)
     int kind;                   // kKindRow or kKindTile
     int cap_is_error;           // 0 when the kinetic table is the cost's whole support
+    int fast;                   // claim kernel (mechanical cost only)
+    int quad;                   // the cost is the mechanical c s^2 - p s (window guesses)
+    double cq;                  // c = dx^2 / (2 tau): k(s) = c s^2 - p s
+    double inv2c;               // 1 / (2c)
+    double pofs;                // p / (2c) = P tau / dx
 };
 
 constexpr int kKindRow = 0;     // whole line in LDS, unit stride, window from the line itself
@@ -73,7 +84,11 @@ hipError_t launch_potential_diffs(const double* V, int ndim, const int64_t* n, d
 hipError_t launch_sweep(int method, const double* in, double* out, const SweepArgs& a,
                         hipStream_t s);
 
-// row kernel LDS capacity (doubles) -- lines longer than this use the tile kernel
-constexpr int64_t kRowLdsMax = 12288;
+hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double cq, double inv2c,
+                       double pofs, hipStream_t s);
+size_t fast_lds_for(int kind, int64_t N, int tile_rows, int H);
+void row_layout(int64_t N, int halo, int* nr, int* RS, int* H);
+size_t row_lds_bytes(int64_t N, int halo);
+size_t tile_lds_bytes(int halo);
 
 }  // namespace lo

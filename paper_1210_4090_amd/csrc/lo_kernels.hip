@@ -19,135 +19,17 @@
 // min-plus sweep along another axis never increases the differences along
 // this one and the potential step adds at most tau * max(V(x) - V(x + e_a)).
 #include "lo_internal.h"
+#include "lo_device.h"
 
 #include <math.h>
+
+#include <algorithm>
 
 namespace lo {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kWave = 64;
-constexpr uint64_t kSign = 0x8000000000000000ull;
-
-__device__ __forceinline__ uint64_t enc(double x)
-{
-    uint64_t b = (uint64_t)__double_as_longlong(x);
-    return (b & kSign) ? ~b : (b | kSign);
-}
-
-__device__ __forceinline__ double dec(uint64_t k)
-{
-    uint64_t b = (k & kSign) ? (k & ~kSign) : ~k;
-    return __longlong_as_double((long long)b);
-}
-
-__device__ __forceinline__ uint64_t enc_neg_inf()
-{
-    return ~(uint64_t)0xFFF0000000000000ull;
-}
-
-__device__ __forceinline__ double wave_max(double v)
-{
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-    return v;
-}
-
-// Block-wide max of three values; result valid in every thread.
-__device__ void block_max3(double& a, double& b, double& c, double* red)
-{
-    a = wave_max(a);
-    b = wave_max(b);
-    c = wave_max(c);
-    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
-    const int nw = blockDim.x / kWave;
-    __syncthreads();
-    if (l == 0) {
-        red[w] = a;
-        red[8 + w] = b;
-        red[16 + w] = c;
-    }
-    __syncthreads();
-    a = red[0];
-    b = red[8];
-    c = red[16];
-    for (int i = 1; i < nw; i++) {
-        a = fmax(a, red[i]);
-        b = fmax(b, red[8 + i]);
-        c = fmax(c, red[16 + i]);
-    }
-    __syncthreads();
-}
-
-// Largest W in [0, kcap] such that every s = 1..W passes the test
-//   level == false:  k(dir s) - k(dir (s-1)) <= D + slack   (neighbour comparison)
-//   level == true:   k(dir s) - k(0)         <= D + slack   (comparison with e = 0)
-// with slack = 2^-40 (sbase + |k(dir s)| + |other|).  Executed by one full
-// wave.  *cap is set when the table ends before a failure.
-__device__ int window_side(const double* __restrict__ k, int64_t kcap, int dir, double D,
-                           double sbase, bool level, bool* cap)
-{
-    const int lane = threadIdx.x % kWave;
-    const double k0 = k[0];
-    for (int64_t base = 0; base < kcap; base += kWave) {
-        const int64_t s = base + lane + 1;
-        bool fail = true;
-        if (s <= kcap) {
-            const double a = k[dir * s], b = level ? k0 : k[dir * (s - 1)];
-            const double d = a - b;
-            const double lim = D + (sbase + fabs(a) + fabs(b)) * 0x1p-40;
-            fail = !(d <= lim);
-        }
-        const uint64_t m = __ballot(fail);
-        if (m) {
-            const int first = __ffsll((unsigned long long)m) - 1;
-            const int64_t sf = base + first + 1;
-            if (sf > kcap) {
-                *cap = true;
-                return (int)kcap;
-            }
-            return (int)(sf - 1);
-        }
-    }
-    *cap = true;
-    return (int)kcap;
-}
-
-// Computes (W+, W-) for this block and broadcasts them through shared memory:
-// the smaller of the neighbour bound (max differences Dp, Dm) and the level
-// bound (oscillation osc of the sweep input).
-__device__ void block_window(const SweepArgs& a, double Dp, double Dm, double osc, double M, int* shw)
-{
-    if (threadIdx.x < kWave) {
-        int wp, wm;
-        bool cap = false;
-        if (a.wfix > 0) {
-            wp = wm = a.wfix;
-        } else {
-            const double sbase = 1.0 + M + a.slack_extra;
-            bool c1 = false, c2 = false, c3 = false, c4 = false;
-            const int lp = window_side(a.kin.k, a.kin.kcap, +1, Dp, sbase, false, &c1);
-            const int op = window_side(a.kin.k, a.kin.kcap, +1, osc, sbase, true, &c2);
-            const int lm = window_side(a.kin.k, a.kin.kcap, -1, Dm, sbase, false, &c3);
-            const int om = window_side(a.kin.k, a.kin.kcap, -1, osc, sbase, true, &c4);
-            wp = min(lp, op);
-            wm = min(lm, om);
-            cap = (c1 && c2) || (c3 && c4);
-        }
-        if (threadIdx.x == 0) {
-            shw[0] = wp;
-            shw[1] = wm;
-            if (cap && a.cap_is_error) atomicOr(&a.flags[0], kErrWindowCap);
-            atomicMax(&a.flags[1 + a.axis], (uint32_t)max(wp, wm));
-        }
-    }
-    __syncthreads();
-}
-
-__device__ __forceinline__ void clear_slot(uint64_t* slot)
-{
-    if (slot && blockIdx.x == 0 && threadIdx.x < kSlotWords) slot[threadIdx.x] = enc_neg_inf();
-}
+using namespace dev;
 
 __device__ __forceinline__ void record_arg(const SweepArgs& a, int64_t idx, int e, int& amax)
 {
@@ -159,134 +41,184 @@ __device__ __forceinline__ void record_arg(const SweepArgs& a, int64_t idx, int 
     amax = max(amax, abs(e));
 }
 
-// Minimum update: values only, or value and lowest candidate index (strict <
-// keeps the first of equal values; candidates are visited in increasing e).
+// Minimum update: values only, or value and lowest candidate offset (strict <
+// keeps the first of equal values; candidates arrive in increasing offset).
 template <int ARG>
-__device__ __forceinline__ void take(double& best, int& arg, double v, int q)
+__device__ __forceinline__ void take(double& best, int& arg, double v, int e)
 {
     if (ARG) {
         if (v < best) {
             best = v;
-            arg = q;
+            arg = e;
         }
     } else {
         best = fmin(best, v);
     }
 }
 
-// Window loop over candidates q = 0 .. ne-1 (offset e = q - wp) for TB
-// targets whose first candidate sits at src[k][0], consecutive candidates
-// `step` doubles apart in LDS.  kr[-q] is the kinetic cost of candidate q;
-// it is the same for every lane, so it comes through scalar loads.
-template <int ARG, int TB>
-__device__ __forceinline__ void window_loop(const double* const (&src)[TB], int step, int ne,
-                                            const double* __restrict__ kr, double (&best)[TB],
-                                            int (&arg)[TB])
+// Register-blocked window loop.  A thread owns TB consecutive targets
+// base .. base+TB-1 of a line; source base+q (q = -wp .. TB-1+wm) is read
+// from LDS once, at lds[lane + off(q)], and offered to all TB targets with
+// the kinetic cost k(k - q) of target base+k.  Every target thereby sees a
+// superset of its window [-wp, wm]: the extra candidates are genuine lifted
+// sources, and none of them can tie the minimum (all minimisers lie inside
+// the window), so values and lowest offsets are those of the window.  The
+// costs depend only on (k, q), the same in every lane: scalar loads.
+template <int ARG, int TB, class Off>
+__device__ __forceinline__ void blocked_loop(const double* lds, int lane, Off off, int wp, int wm,
+                                             const double* __restrict__ kc, double (&best)[TB], int (&arg)[TB])
 {
-    int q = 0;
-    for (; q + 8 <= ne; q += 8) {
-        double kv[8];
+    const int qhi = TB - 1 + wm;
+    int q = -wp;
+    for (; q + 1 <= qhi; q += 2) {
+        const double* __restrict__ kq = kc - q - 1;   // kq[i] = k(i - q - 1)
+        double kv[TB + 1];
 #pragma unroll
-        for (int t = 0; t < 8; t++) kv[t] = kr[-(q + t)];
+        for (int i = 0; i <= TB; i++) kv[i] = kq[i];
+        const double v0 = lds[lane + off(q)];
+        const double v1 = lds[lane + off(q + 1)];
 #pragma unroll
-        for (int t = 0; t < 8; t++) {
-#pragma unroll
-            for (int k = 0; k < TB; k++) take<ARG>(best[k], arg[k], src[k][(q + t) * step] + kv[t], q + t);
+        for (int k = 0; k < TB; k++) {
+            take<ARG>(best[k], arg[k], v0 + kv[k + 1], q - k);
+            take<ARG>(best[k], arg[k], v1 + kv[k], q + 1 - k);
         }
     }
-    for (; q < ne; q++) {
-        const double kv = kr[-q];
+    if (q <= qhi) {
+        const double v0 = lds[lane + off(q)];
 #pragma unroll
-        for (int k = 0; k < TB; k++) take<ARG>(best[k], arg[k], src[k][q * step] + kv, q);
+        for (int k = 0; k < TB; k++) take<ARG>(best[k], arg[k], v0 + kc[k - q], q - k);
     }
 }
 
+constexpr int kTB = 8;          // consecutive targets per thread
+constexpr int kTileC = 16;      // lines per tile (16 doubles = one 128-byte line)
+constexpr int kTileRP = kBlock / kTileC;
+constexpr int kTileR = kTileRP * kTB;   // real targets per tile: 128
+
 // ---------------------------------------------------------------------------
-// Row sweep (axis 0, unit stride): one block per row, the whole row plus a
-// wrapped halo of H cells on each side in LDS.  The window comes from the row
-// itself.  Threads own targets tid, tid+256, ...; the candidate offset e is
-// the same in every lane, so the kinetic cost k(-e) is a scalar load.
+// Row sweep (axis 0, unit stride).  A block holds nr whole rows (nr * N =
+// 256 * TB when N divides 2048, else one row in passes of 2048 targets) with
+// a wrapped halo of H cells, in a skewed layout: element j of a row sits at
+// (j + H) + (j + H) / TB, so the TB-strided reads of the blocked loop hit
+// distinct banks.  The window is the widest over the block's rows, each from
+// the row itself.
 // ---------------------------------------------------------------------------
-template <int ARG, int EPI, int TB>
-__global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__ in,
-                                                      double* __restrict__ out,
-                                                      const double* __restrict__ kc, SweepArgs a, int H)
+__device__ __forceinline__ int skew(int x) { return x + x / kTB; }
+
+template <int ARG, int EPI>
+__global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__ in, double* __restrict__ out,
+                                                      const double* __restrict__ kc, SweepArgs a, int H, int nr,
+                                                      int RS)
 {
     extern __shared__ double sm[];
     __shared__ double red[24];
     __shared__ int shw[2];
-    const int64_t N = a.g.n;
-    const int64_t row = blockIdx.x;
-    const double* __restrict__ src = in + row * N;
-    double* lrow = sm + H;
+    const int N = (int)a.g.n;
+    const int lpr = nr > 1 ? N / kTB : kBlock;          // lanes per row
+    const int rb = threadIdx.x / lpr, lr = threadIdx.x % lpr;
+    const int64_t row0 = (int64_t)blockIdx.x * nr;
+    const int nrow = (int)min((int64_t)nr, a.g.nlines - row0);
+    const int span = N + 2 * H;
 
     clear_slot(a.stats_clear);
-    for (int64_t p = (int64_t)threadIdx.x - H; p < N + H; p += blockDim.x) {
-        int64_t q = p < 0 ? p + N : (p >= N ? p - N : p);
-        lrow[p] = src[q];
+    for (int r = 0; r < nrow; r++) {
+        const double* __restrict__ src = in + (row0 + r) * N;
+        double* dst = sm + r * RS;
+        int q = ((int)threadIdx.x - H) % N;   // source of jj = threadIdx.x, wrapped into [0, N)
+        if (q < 0) q += N;
+        for (int jj = threadIdx.x; jj < span; jj += kBlock) {
+            dst[skew(jj)] = src[q];
+            q += kBlock;
+            while (q >= N) q -= N;
+        }
     }
     __syncthreads();
 
     double dp = -INFINITY, dm = -INFINITY, am = 0.0, hi = -INFINITY, nlo = -INFINITY;
     if (a.wfix <= 0) {
-        for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-            const double x = lrow[i], y = lrow[i + 1];
-            dp = fmax(dp, y - x);
-            dm = fmax(dm, x - y);
-            am = fmax(am, fabs(x));
-            hi = fmax(hi, x);
-            nlo = fmax(nlo, -x);
+        if (rb < nrow) {
+            const double* R = sm + rb * RS;
+            for (int i = lr; i < N; i += lpr) {
+                const double x = R[skew(i + H)], y = R[skew(i + 1 + H)];
+                dp = fmax(dp, y - x);
+                dm = fmax(dm, x - y);
+                am = fmax(am, fabs(x));
+                hi = fmax(hi, x);
+                nlo = fmax(nlo, -x);
+            }
         }
         block_max3(dp, dm, am, red);
         double t = 0.0;
         block_max3(hi, nlo, t, red);
     }
-    block_window(a, dp, dm, hi + nlo, am, shw);
+    block_window(a, nullptr, dp, dm, hi + nlo, am, shw);
     const int wp = __builtin_amdgcn_readfirstlane(shw[0]);
     const int wm = __builtin_amdgcn_readfirstlane(shw[1]);
     const bool inlds = wp <= H && wm <= H;
-    const double* __restrict__ kr = kc + wp;   // kr[-q] = k(-(q - wp))
-    const int ne = wp + wm + 1;
     int amax = 0;
 
-    for (int64_t i0 = 0; i0 < N; i0 += (int64_t)TB * blockDim.x) {
-        int64_t it[TB];
-        double best[TB];
-        int arg[TB];
+    const int per_pass = lpr * kTB;
+    for (int i0 = 0; i0 < N; i0 += per_pass) {
+        const int tbase = i0 + lr * kTB;
+        double best[kTB];
+        int arg[kTB];
 #pragma unroll
-        for (int k = 0; k < TB; k++) {
-            it[k] = i0 + threadIdx.x + (int64_t)k * blockDim.x;
+        for (int k = 0; k < kTB; k++) {
             best[k] = INFINITY;
             arg[k] = 0;
         }
+        const bool live = rb < nrow && tbase < N;
         if (inlds) {
-            const double* sp[TB];
+            // lane part of the skewed address of element tbase + q
+            const int lane = live ? rb * RS + (tbase / kTB) * (kTB + 1) : 0;
+            blocked_loop<ARG, kTB>(sm, lane, [H](int q) { return skew(H + q); }, wp, wm, kc, best, arg);
+        } else if (live) {
+            const double* R = sm + rb * RS;
 #pragma unroll
-            for (int k = 0; k < TB; k++) sp[k] = lrow + (it[k] < N ? it[k] : N - 1) - wp;
-            window_loop<ARG, TB>(sp, 1, ne, kr, best, arg);
-        } else {
-            // window wider than the halo: wrap source indices explicitly
-#pragma unroll
-            for (int k = 0; k < TB; k++) {
-                if (it[k] >= N) continue;
-                int64_t j = (it[k] - wp) % N;
+            for (int k = 0; k < kTB; k++) {
+                int j = (tbase + k - wp) % N;
                 if (j < 0) j += N;
-                for (int q = 0; q < ne; ++q) {
-                    take<1>(best[k], arg[k], lrow[j] + kr[-q], q);
+                for (int e = -wp; e <= wm; ++e) {
+                    take<1>(best[k], arg[k], R[skew(j + H)] + kc[-e], e);
                     if (++j == N) j = 0;
                 }
             }
         }
+        __syncthreads();   // all reads of this pass' sources done before outputs overwrite them
+        // stage outputs in natural order, then store coalesced
+        double* W = sm + rb * RS;
+        int* A = (int*)(sm + (size_t)nr * RS) + rb * per_pass;
+        if (live) {
 #pragma unroll
-        for (int k = 0; k < TB; k++) {
-            if (it[k] >= N) continue;
-            const int64_t idx = row * N + it[k];
-            double w = best[k];
+            for (int k = 0; k < kTB; k++) {
+                W[skew(lr * kTB + k)] = best[k];
+                if (ARG) A[lr * kTB + k] = arg[k];
+            }
+        }
+        __syncthreads();
+        const int cnt = min(per_pass, N - i0);
+        for (int t = lr; t < cnt && rb < nrow; t += lpr) {
+            const int64_t idx = (row0 + rb) * N + i0 + t;
+            double w = W[skew(t)];
             if (EPI) w = w - a.hv[idx];
             out[idx] = w;
-            const int e = arg[k] - wp;
-            if (ARG && a.argmin) record_arg(a, idx, e, amax);
-            if (ARG && a.wfix > 0 && (e == -wp || e == wm)) atomicOr(&a.flags[0], kErrWindowEdge);
+            if (ARG) {
+                const int e = A[t];
+                if (a.argmin) record_arg(a, idx, e, amax);
+                if (a.wfix > 0 && (e == -wp || e == wm)) atomicOr(&a.flags[0], kErrWindowEdge);
+            }
+        }
+        if (i0 + per_pass < N) {
+            // reload this row's sources for the next pass (outputs overwrote them)
+            __syncthreads();
+            int q = ((int)threadIdx.x - H) % N;
+            if (q < 0) q += N;
+            for (int jj = threadIdx.x; jj < span; jj += kBlock) {
+                sm[skew(jj)] = in[row0 * N + q];
+                q += kBlock;
+                while (q >= N) q -= N;
+            }
+            __syncthreads();
         }
     }
     if (ARG && a.argmin) {
@@ -296,40 +228,32 @@ __global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Tile sweep (any axis, any stride): a block owns C consecutive lines and R
-// consecutive targets; sources [r0 - H, r0 + R + H] are staged in LDS as
-// [row][line] (consecutive lanes = consecutive lines = consecutive
-// addresses).  Windows wider than H read sources straight from global memory.
-// Each tile also evaluates one extra target (r0 + R) so that the forward
-// differences of the output along the axis can be bounded for the next step.
+// Tile sweep (any axis, any stride): a block owns 16 consecutive lines and
+// 128 consecutive targets; the window comes first (from the stats slot), then
+// only the sources [r0 - W+, r0 + 128 + W-] are staged in LDS as [row][line]
+// (16 lanes = 16 consecutive lines = one 128-byte segment).  Each thread owns
+// 8 consecutive targets of one line.  Windows wider than the halo read
+// sources straight from global memory.  Lanes of row group 0 also evaluate
+// target r0 + Rt (the next tile's first), so the forward differences of the
+// output along the axis -- the next step's window bound -- are complete.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t remap_block(int64_t b, int64_t G)
-{
-    // consecutive tiles of the same lines go to one XCD (blocks are dealt to
-    // the 8 XCDs round robin), so their shared halo rows hit in its L2
-    if (G % 8 != 0) return b;
-    return (b % 8) * (G / 8) + b / 8;
-}
-
-template <int ARG, int EPI, int C, int TB>
-__global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict__ in,
-                                                       double* __restrict__ out,
+template <int ARG, int EPI>
+__global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict__ in, double* __restrict__ out,
                                                        const double* __restrict__ kc, SweepArgs a)
 {
     extern __shared__ double sm[];
     __shared__ double red[24];
     __shared__ int shw[2];
-    constexpr int RP = kBlock / C;  // target rows per pass
+    __shared__ double fv[kTileRP + 1][kTileC];
+    constexpr int C = kTileC;
     const int64_t N = a.g.n, S = a.g.stride;
-    const int H = a.halo, R = a.tile_rows;
-    const int64_t nTB = (N + R - 1) / R;
+    const int H = a.halo;
+    const int64_t nTB = (N + kTileR - 1) / kTileR;
     const int64_t nLB = (a.g.nlines + C - 1) / C;
     const int64_t b = remap_block(blockIdx.x, nTB * nLB);
     const int64_t lb = b / nTB, tb = b % nTB;
-    const int64_t r0 = tb * R;
-    const int Rt = (int)min((int64_t)R, N - r0);    // real targets of this tile
-    double* tile = sm;                               // (R + 2H + 1) * C
-    double* wbuf = sm + (size_t)(R + 2 * H + 1) * C;  // (R + 1) * C
+    const int64_t r0 = tb * kTileR;
+    const int Rt = (int)min((int64_t)kTileR, N - r0);   // real targets of this tile
 
     const int c = threadIdx.x % C;
     const int rr = threadIdx.x / C;
@@ -339,68 +263,78 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
     const int64_t base = inner + S * N * outer;
 
     clear_slot(a.stats_clear);
-    for (int p = rr; p <= Rt + 2 * H; p += RP) {
-        int64_t q = r0 - H + p;
-        q %= N;
-        if (q < 0) q += N;
-        tile[p * C + c] = lv ? in[base + S * q] : 0.0;
-    }
-    double dp = -INFINITY, dm = -INFINITY, mm = -INFINITY, osc = INFINITY;
-    if (a.wfix <= 0) {
-        dp = dec(a.stats_in[a.axis]) + a.dv_fwd;
-        dm = dec(a.stats_in[3 + a.axis]) + a.dv_bwd;
-        mm = dec(a.stats_in[6]);
-        osc = (dec(a.stats_in[7]) + dec(a.stats_in[8])) + a.osc_extra;
-    }
-    block_window(a, dp, dm, osc, mm, shw);  // ends with __syncthreads: the tile is staged
+    block_window(a, a.stats_in, 0.0, 0.0, 0.0, 0.0, shw);
     const int wp = __builtin_amdgcn_readfirstlane(shw[0]);
     const int wm = __builtin_amdgcn_readfirstlane(shw[1]);
     const bool inlds = wp <= H && wm <= H;
-    const double* __restrict__ kr = kc + wp;
-    const int ne = wp + wm + 1;
-    int amax = 0;
-
-    for (int rb = 0; rb <= Rt; rb += TB * RP) {
-        int rk[TB];
-        double best[TB];
-        int arg[TB];
-#pragma unroll
-        for (int k = 0; k < TB; k++) {
-            rk[k] = rb + rr + k * RP;
-            best[k] = INFINITY;
-            arg[k] = 0;
+    if (inlds) {
+        int64_t q = (r0 - wp + rr) % N;   // source of row p = H - wp + rr
+        if (q < 0) q += N;
+        const double* __restrict__ src = in + base;
+        for (int p = H - wp + rr; p <= H + kTileR + wm; p += kTileRP) {
+            sm[p * C + c] = lv ? src[S * q] : 0.0;
+            q += kTileRP;
+            while (q >= N) q -= N;
         }
-        if (inlds) {
-            const double* sp[TB];
+        __syncthreads();
+    }
+
+    double best[kTB];
+    int arg[kTB];
 #pragma unroll
-            for (int k = 0; k < TB; k++) sp[k] = tile + (size_t)((rk[k] <= Rt ? rk[k] : Rt) + H - wp) * C + c;
-            window_loop<ARG, TB>(sp, C, ne, kr, best, arg);
-        } else if (lv) {
+    for (int k = 0; k < kTB; k++) {
+        best[k] = INFINITY;
+        arg[k] = 0;
+    }
+    const int tbase = rr * kTB;
+    double bnd = INFINITY;   // target r0 + Rt, evaluated by row group 0
+    int bnd_arg = 0;
+    if (inlds) {
+        blocked_loop<ARG, kTB>(sm, tbase * C + c, [H](int q) { return (H + q) * C; }, wp, wm, kc, best, arg);
+        if (rr == 0) {
+            const double* col = sm + (size_t)(Rt + H) * C + c;
+            for (int e = -wp; e <= wm; ++e) take<ARG>(bnd, bnd_arg, col[e * C] + kc[-e], e);
+        }
+    } else if (lv) {
+        // window wider than the halo: every candidate from global memory
 #pragma unroll
-            for (int k = 0; k < TB; k++) {
-                if (rk[k] > Rt) continue;
-                int64_t j = (r0 + rk[k] - wp) % N;
+        for (int k = 0; k <= kTB; k++) {
+            const int t = k < kTB ? tbase + k : Rt;
+            const bool want = k < kTB ? t < Rt : rr == 0;
+            double bb = INFINITY;
+            int aa = 0;
+            if (want) {
+                int64_t j = (r0 + t - wp) % N;
                 if (j < 0) j += N;
-                for (int q = 0; q < ne; ++q) {
-                    take<1>(best[k], arg[k], in[base + S * j] + kr[-q], q);
+                for (int e = -wp; e <= wm; ++e) {
+                    take<1>(bb, aa, in[base + S * j] + kc[-e], e);
                     if (++j == N) j = 0;
                 }
             }
-        }
+            // register arrays stay in registers only with compile-time indices
 #pragma unroll
-        for (int k = 0; k < TB; k++) {
-            const int r = rk[k];
-            if (r > Rt) continue;
-            wbuf[r * C + c] = best[k];
-            if (r < Rt && lv) {
-                const int64_t idx = base + S * (r0 + r);
-                double w = best[k];
-                if (EPI) w = w - a.hv[idx];
-                out[idx] = w;
-                const int e = arg[k] - wp;
-                if (ARG && a.argmin) record_arg(a, idx, e, amax);
-                if (ARG && a.wfix > 0 && (e == -wp || e == wm)) atomicOr(&a.flags[0], kErrWindowEdge);
+            for (int kk = 0; kk < kTB; kk++) {
+                if (kk == k) {
+                    best[kk] = bb;
+                    arg[kk] = aa;
+                }
             }
+            if (k == kTB) bnd = bb;
+        }
+    }
+
+    int amax = 0;
+    if (lv) {
+#pragma unroll
+        for (int k = 0; k < kTB; k++) {
+            const int t = tbase + k;
+            if (t >= Rt) continue;
+            const int64_t idx = base + S * (r0 + t);
+            double w = best[k];
+            if (EPI) w = w - a.hv[idx];
+            out[idx] = w;
+            if (ARG && a.argmin) record_arg(a, idx, arg[k], amax);
+            if (ARG && a.wfix > 0 && (arg[k] == -wp || arg[k] == wm)) atomicOr(&a.flags[0], kErrWindowEdge);
         }
     }
     if (ARG && a.argmin) {
@@ -408,16 +342,27 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
         if (threadIdx.x % kWave == 0) atomicMax(&a.flags[4 + a.axis], (uint32_t)amax);
     }
     if (a.stats_out) {
+        // forward differences of this sweep's output along the axis
+        fv[rr][c] = best[0];
+        if (rr == 0) fv[kTileRP][c] = bnd;
         __syncthreads();
         double sp = -INFINITY, sn = -INFINITY, sa = 0.0, hi = -INFINITY, nlo = -INFINITY;
         if (lv) {
-            for (int r = rr; r < Rt; r += RP) {
-                const double x = wbuf[r * C + c], y = wbuf[(r + 1) * C + c];
+            double nx[kTB];
+#pragma unroll
+            for (int k = 0; k + 1 < kTB; k++) nx[k] = best[k + 1];
+            nx[kTB - 1] = fv[rr + 1 <= kTileRP ? rr + 1 : kTileRP][c];
+#pragma unroll
+            for (int k = 0; k < kTB; k++) {
+                const int t = tbase + k;
+                if (t >= Rt) continue;
+                const double x = best[k];
+                const double y = (t + 1 == Rt) ? fv[kTileRP][c] : nx[k];
                 sp = fmax(sp, y - x);
                 sn = fmax(sn, x - y);
                 sa = fmax(sa, fabs(x));
                 if (EPI) {
-                    const double z = x - a.hv[base + S * (r0 + r)];
+                    const double z = x - a.hv[base + S * (r0 + t)];
                     sa = fmax(sa, fabs(z));
                     hi = fmax(hi, z);
                     nlo = fmax(nlo, -z);
@@ -430,12 +375,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
             block_max3(hi, nlo, t, red);
         }
         if (threadIdx.x == 0) {
-            atomicMax((unsigned long long*)&a.stats_out[a.axis], (unsigned long long)enc(sp));
-            atomicMax((unsigned long long*)&a.stats_out[3 + a.axis], (unsigned long long)enc(sn));
-            atomicMax((unsigned long long*)&a.stats_out[6], (unsigned long long)enc(sa));
+            stat_put(a.stats_out, a.axis, sp);
+            stat_put(a.stats_out, 3 + a.axis, sn);
+            stat_put(a.stats_out, 6, sa);
             if (EPI) {
-                atomicMax((unsigned long long*)&a.stats_out[7], (unsigned long long)enc(hi));
-                atomicMax((unsigned long long*)&a.stats_out[8], (unsigned long long)enc(nlo));
+                stat_put(a.stats_out, 7, hi);
+                stat_put(a.stats_out, 8, nlo);
             }
         }
     }
@@ -446,8 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
 // ---------------------------------------------------------------------------
 __global__ void k_clear_slots(uint64_t* stats)
 {
-    const int i = threadIdx.x;
-    if (i < kSlots * kSlotWords) stats[i] = enc_neg_inf();
+    for (int i = threadIdx.x; i < kSlots * kSlotStride; i += blockDim.x) stats[i] = enc_neg_inf();
 }
 
 // Max forward / backward difference along every axis and max |u| of u.
@@ -482,12 +426,12 @@ __global__ __launch_bounds__(kBlock) void k_stats(const double* __restrict__ u, 
     block_max3(am, hi, nlo, red);
     if (threadIdx.x == 0) {
         for (int ax = 0; ax < ndim; ax++) {
-            atomicMax((unsigned long long*)&slot[ax], (unsigned long long)enc(dp[ax]));
-            atomicMax((unsigned long long*)&slot[3 + ax], (unsigned long long)enc(dm[ax]));
+            stat_put(slot, ax, dp[ax]);
+            stat_put(slot, 3 + ax, dm[ax]);
         }
-        atomicMax((unsigned long long*)&slot[6], (unsigned long long)enc(am));
-        atomicMax((unsigned long long*)&slot[7], (unsigned long long)enc(hi));
-        atomicMax((unsigned long long*)&slot[8], (unsigned long long)enc(nlo));
+        stat_put(slot, 6, am);
+        stat_put(slot, 7, hi);
+        stat_put(slot, 8, nlo);
     }
 }
 
@@ -558,30 +502,48 @@ int grid_for(int64_t npts)
 template <int ARG, int EPI>
 hipError_t launch_row(const double* in, double* out, const SweepArgs& a, hipStream_t s)
 {
-    const int64_t N = a.g.n;
-    const int H = (int)(N < (int64_t)a.halo ? N : (int64_t)a.halo);
-    const size_t lds = sizeof(double) * (size_t)(N + 2 * H);
-    hipLaunchKernelGGL((k_row_brute<ARG, EPI, 4>), dim3((unsigned)a.g.nlines), dim3(kBlock), lds, s, in,
-                       out, a.kin.k, a, H);
+    int nr, RS, H;
+    row_layout(a.g.n, a.halo, &nr, &RS, &H);
+    const size_t lds = row_lds_bytes(a.g.n, a.halo);
+    const int64_t G = (a.g.nlines + nr - 1) / nr;
+    hipLaunchKernelGGL((k_row_brute<ARG, EPI>), dim3((unsigned)G), dim3(kBlock), lds, s, in, out, a.kin.k, a, H,
+                       nr, RS);
     return hipGetLastError();
 }
 
 template <int ARG, int EPI>
 hipError_t launch_tile(const double* in, double* out, const SweepArgs& a, hipStream_t s)
 {
-    constexpr int C = 16;
-    const int64_t N = a.g.n;
-    const int R = a.tile_rows, H = a.halo;
-    const int64_t G = ((N + R - 1) / R) * ((a.g.nlines + C - 1) / C);
-    const size_t lds = sizeof(double) * ((size_t)(R + 2 * H + 1) * C + (size_t)(R + 1) * C);
-    hipLaunchKernelGGL((k_tile_brute<ARG, EPI, C, 4>), dim3((unsigned)G), dim3(kBlock), lds, s, in, out,
-                       a.kin.k, a);
+    const int64_t G = ((a.g.n + kTileR - 1) / kTileR) * ((a.g.nlines + kTileC - 1) / kTileC);
+    hipLaunchKernelGGL((k_tile_brute<ARG, EPI>), dim3((unsigned)G), dim3(kBlock), tile_lds_bytes(a.halo), s, in,
+                       out, a.kin.k, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
+void row_layout(int64_t N, int halo, int* nr, int* RS, int* H)
+{
+    // halo rounded up to a multiple of TB, at most N
+    int h = (int)std::min<int64_t>(N, (int64_t)halo);
+    h = (h + kTB - 1) / kTB * kTB;
+    *H = h;
+    *nr = (N <= 2048 && 2048 % N == 0 && N % kTB == 0) ? (int)(2048 / N) : 1;
+    const int span = (int)N + 2 * h;
+    *RS = span + span / kTB + 1;
+}
+
+size_t row_lds_bytes(int64_t N, int halo)
+{
+    int nr, RS, H;
+    row_layout(N, halo, &nr, &RS, &H);
+    const int per_pass = (nr > 1 ? (int)N / kTB : kBlock) * kTB;
+    return sizeof(double) * (size_t)nr * RS + sizeof(int) * (size_t)nr * per_pass;
+}
+
+size_t tile_lds_bytes(int halo) { return sizeof(double) * (size_t)(kTileR + 2 * halo + 1) * kTileC; }
+
 hipError_t launch_clear_slots(uint64_t* stats, hipStream_t s)
 {
     hipLaunchKernelGGL(k_clear_slots, dim3(1), dim3(64), 0, s, stats);
@@ -620,6 +582,7 @@ hipError_t launch_potential_diffs(const double* V, int ndim, const int64_t* n, d
 hipError_t launch_sweep(int method, const double* in, double* out, const SweepArgs& a, hipStream_t s)
 {
     (void)method;
+    if (a.fast && a.wfix <= 0) return launch_fast(in, out, a, a.cq, a.inv2c, a.pofs, s);
     const bool arg = a.argmin != nullptr || a.wfix > 0;
     const bool epi = a.hv != nullptr;
     const bool row = a.kind == kKindRow;

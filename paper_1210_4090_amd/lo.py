@@ -168,6 +168,15 @@ class Plan:
             check("lo_last_diag", st)
         return list(w[: self.ndim]), list(m[: self.ndim])
 
+    def time_kernels(self, u: torch.Tensor, nsteps: int, n0: int = 0, stream=None):
+        """Mean duration (ms) of each axis' sweep kernel over nsteps steps (HIP events)."""
+        _dev_f64(u, "u", self.shape)
+        ms = np.zeros(3, dtype=np.float64)
+        check("lo_time_kernels", lib().lo_time_kernels(self._h, ctypes.c_void_p(u.data_ptr()), int(n0), int(nsteps),
+                                                       ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                       _stream(stream)))
+        return ms[: self.ndim]
+
     def kinetic_table(self, axis: int, s0: int, count: int) -> np.ndarray:
         out = np.empty(count, dtype=np.float64)
         check("lo_kinetic_table", lib().lo_kinetic_table(self._h, int(axis), int(s0), int(count),

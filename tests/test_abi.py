@@ -20,7 +20,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("lo_plan", "lo_plan_destroy", "lo_step", "lo_run", "lo_effective_H", "lo_backward",
-                     "lo_status_string", "lo_last_diag", "lo_kinetic_table", "lo_set_coef"):
+                     "lo_status_string", "lo_last_diag", "lo_kinetic_table", "lo_set_coef", "lo_time_kernels"):
         assert required in names
 
 
