@@ -45,7 +45,9 @@ struct lo_plan_s {
     double hvmax = 0.0;
     // work
     double* scratch = nullptr;
-    uint64_t* stats = nullptr;   // kSlots * kSlotWords
+    uint64_t* stats = nullptr;   // kSlots * kSlotStride
+    int* win = nullptr;          // windows of the current and next step: [2][2 * kMaxDim]
+    WinParams winp;
     uint32_t* flags = nullptr;   // kFlagWords
     uint32_t hflags[8] = {0};    // folded: [0] errors, [1+a] window used, [4+a] max |argmin|
     bool have_diag = false;
@@ -132,6 +134,7 @@ void free_plan(lo_plan_t p)
     if (p->scratch) (void)hipFree(p->scratch);
     if (p->stats) (void)hipFree(p->stats);
     if (p->flags) (void)hipFree(p->flags);
+    if (p->win) (void)hipFree(p->win);
     for (auto& g : p->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -277,7 +280,7 @@ void choose_kernels(lo_plan_t p)
     for (int a = 0; a < p->ndim; a++) {
         const int64_t N = p->n[a];
         p->fast[a] = fast && !p->user_table[a];
-        const bool row_ok = a == 0 && N <= 16384 &&
+        const bool row_ok = a == 0 && N <= 2048 &&
                             (p->fast[a] ? fast_lds_for(kKindRow, N, 0, 1) <= fbudget
                                         : row_lds_bytes(N, 8) <= budget);
         if (row_ok) {
@@ -333,6 +336,28 @@ void sweep_buffers(lo_plan_t p, double* u, double* in[kMaxDim], double* out[kMax
     }
 }
 
+void fill_winparams(lo_plan_t p)
+{
+    WinParams& W = p->winp;
+    memset(&W, 0, sizeof(W));
+    W.ndim = p->ndim;
+    W.slack_extra = slack_extra(p);
+    double drop = 0.0;   // a sweep raises the max by at most k(0) and lowers the min by at most -min k
+    for (int a = 0; a < p->ndim; a++) {
+        W.k[a] = p->dkt[a] + p->kcap[a];
+        W.kcap[a] = p->kcap[a];
+        W.dvf[a] = p->dvf[a];
+        W.dvb[a] = p->dvb[a];
+        W.osc_extra[a] = drop;
+        drop += p->kzero_drop[a];
+        W.cq[a] = p->dx[a] * p->dx[a] / (2.0 * p->d.tau);
+        W.pofs[a] = p->d.P[a] * p->d.tau / p->dx[a];
+        W.quad[a] = p->user_table[a] ? 0 : 1;
+        W.cap_err[a] = p->user_table[a] ? 0 : 1;
+        W.wfix[a] = p->d.window[a];
+    }
+}
+
 // The device's one-sided window search, on the host table (for sizing halos).
 int host_side(const std::vector<double>& t, int64_t kcap, int dir, double D, double sbase, bool level)
 {
@@ -352,23 +377,50 @@ int choose_halo(lo_plan_t p, int a, int W)
     return std::max(8, std::min(H, p->halo_max[a]));
 }
 
-// Initial halos from the window bound of the state in stats slot n0.
-lo_status adapt_from_slot(lo_plan_t p, int64_t n0)
+// Windows of step n0 from the statistics of u in stats slot n0 (the same
+// bounds the last block of every step computes on the device), uploaded to the
+// step's window slot; halos sized from them.
+lo_status adapt_from_slot(lo_plan_t p, int64_t n0, hipStream_t s)
 {
     std::vector<uint64_t> raw(kSlotStride);
     HIPCHK(hipMemcpy(raw.data(), slot(p, n0), sizeof(uint64_t) * kSlotStride, hipMemcpyDeviceToHost));
     double h[kSlotWords];
     fold_slot(raw.data(), h);
     const double M = h[6];
-    double osc = h[7] + h[8];
+    const double osc0 = h[7] + h[8];
+    int win[2 * kMaxDim] = {0, 0, 0, 0, 0, 0};
     for (int a = 0; a < p->ndim; a++) {
-        const double sbase = 1.0 + M + slack_extra(p);
-        const double Dp = h[a] + p->dvf[a], Dm = h[3 + a] + p->dvb[a];
-        const int64_t kc = p->kcap[a];
-        const int wp = std::min(host_side(p->hkt[a], kc, 1, Dp, sbase, false), host_side(p->hkt[a], kc, 1, osc, sbase, true));
-        const int wm = std::min(host_side(p->hkt[a], kc, -1, Dm, sbase, false), host_side(p->hkt[a], kc, -1, osc, sbase, true));
+        int wp, wm;
+        if (p->d.window[a] > 0) {
+            wp = wm = p->d.window[a];
+        } else {
+            const double sbase = 1.0 + M + p->winp.slack_extra;
+            const double Dp = h[a] + p->dvf[a], Dm = h[3 + a] + p->dvb[a];
+            const double osc = osc0 + p->winp.osc_extra[a];
+            const int64_t kc = p->kcap[a];
+            wp = std::min(host_side(p->hkt[a], kc, 1, Dp, sbase, false), host_side(p->hkt[a], kc, 1, osc, sbase, true));
+            wm = std::min(host_side(p->hkt[a], kc, -1, Dm, sbase, false),
+                          host_side(p->hkt[a], kc, -1, osc, sbase, true));
+            if (p->winp.cap_err[a] && (wp >= kc || wm >= kc)) {
+                // the bound reached the table's end: the definition's minimisers may lie beyond it
+                const bool capp = host_side(p->hkt[a], kc, 1, Dp, sbase, false) >= kc &&
+                                  host_side(p->hkt[a], kc, 1, osc, sbase, true) >= kc;
+                const bool capm = host_side(p->hkt[a], kc, -1, Dm, sbase, false) >= kc &&
+                                  host_side(p->hkt[a], kc, -1, osc, sbase, true) >= kc;
+                if (capp || capm) p->hflags[0] |= kErrWindowCap;
+            }
+        }
+        win[2 * a] = wp;
+        win[2 * a + 1] = wm;
+        p->hflags[1 + a] = std::max(p->hflags[1 + a], (uint32_t)std::max(wp, wm));
         p->halo[a] = choose_halo(p, a, std::max(wp, wm));
-        osc += p->kzero_drop[a];
+    }
+    int* dst = p->win + (size_t)(((n0 % 2) + 2) % 2) * 2 * kMaxDim;
+    HIPCHK(hipMemcpyAsync(dst, win, sizeof(win), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (p->hflags[0] & kErrWindowCap) {
+        uint32_t e = p->hflags[0];
+        HIPCHK(hipMemcpy(p->flags, &e, sizeof(e), hipMemcpyHostToDevice));
     }
     return LO_OK;
 }
@@ -416,15 +468,13 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.slack_extra = sx;
         A.dv_fwd = p->dvf[a];
         A.dv_bwd = p->dvb[a];
-        // a sweep raises the max by at most k(0) and lowers the min by at most -min k
-        for (int b = 0; b < a; b++) A.osc_extra += p->kzero_drop[b];
+        A.osc_extra = p->winp.osc_extra[a];
         A.kind = p->kind[a];
         A.cap_is_error = p->user_table[a] ? 0 : 1;
-        if (p->kind[a] == kKindTile) {
-            A.stats_in = slot(p, n);
-            A.stats_out = slot(p, n + 1);
-        }
+        A.stats_in = slot(p, n);
+        A.stats_out = slot(p, n + 1);
         A.stats_clear = a == 0 ? slot(p, n + 2) : nullptr;
+        A.win_in = p->win + (size_t)(((n % 2) + 2) % 2) * 2 * kMaxDim;
         A.flags = p->flags;
         A.hv = a == p->ndim - 1 ? hv : nullptr;
         A.argmin = argmin ? argmin + (size_t)a * p->npts : nullptr;
@@ -439,6 +489,8 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         HIPCHK(launch_sweep(p->d.method, in[a], out[a], A, s));
         if (ev) HIPCHK(hipEventRecord(ev[2 * a + 1], s));
     }
+    HIPCHK(launch_windows(p->winp, slot(p, n + 1), p->win + (size_t)((((n + 1) % 2) + 2) % 2) * 2 * kMaxDim,
+                          p->flags, s));
     if (out[p->ndim - 1] != u)
         HIPCHK(hipMemcpyAsync(u, out[p->ndim - 1], sizeof(double) * p->npts, hipMemcpyDeviceToDevice, s));
     return LO_OK;
@@ -451,7 +503,7 @@ lo_status prologue(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
     HIPCHK(launch_stats(u, p->ndim, p->n, slot(p, n0), s));
     HIPCHK(hipStreamSynchronize(s));
     for (int i = 0; i < 8; i++) p->hflags[i] = 0;
-    return adapt_from_slot(p, n0);
+    return adapt_from_slot(p, n0, s);
 }
 
 lo_status finish(lo_plan_t p, hipStream_t s, bool argmin)
@@ -530,12 +582,15 @@ lo_status lo_plan(const lo_desc* desc, const lo_potential* V, lo_plan_t* out)
     if (!st) st = alloc((void**)&p->scratch, sizeof(double) * (size_t)p->npts);
     if (!st) st = alloc((void**)&p->stats, sizeof(uint64_t) * kSlots * kSlotStride);
     if (!st) st = alloc((void**)&p->flags, sizeof(uint32_t) * kFlagWords);
+    if (!st) st = alloc((void**)&p->win, sizeof(int) * 4 * kMaxDim);
+    if (!st && hipMemset(p->win, 0, sizeof(int) * 4 * kMaxDim) != hipSuccess) st = LO_ERR_HIP;
     if (!st) st = setup_potential(p, V);
     if (st) {
         free_plan(p);
         return st;
     }
     choose_kernels(p);
+    fill_winparams(p);
     *out = p;
     return LO_OK;
 }
@@ -556,6 +611,7 @@ lo_status lo_set_coef(lo_plan_t p, const double* coef)
     lo_status st = add_potential_margins(p, p->dhv, true);
     if (st) return st;
     HIPCHK(hipDeviceSynchronize());
+    fill_winparams(p);
     return LO_OK;
 }
 

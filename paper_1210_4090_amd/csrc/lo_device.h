@@ -143,64 +143,63 @@ __device__ inline int window_side(const double* __restrict__ k, int64_t kcap, in
     return (int)kcap;
 }
 
-// (W+, W-) for the block, broadcast through shw[0..1]: the smaller of the
-// neighbour bound (max differences Dp, Dm) and the oscillation bound.  The
-// four one-sided searches run in four waves at once.  With a stats slot the
-// inputs are read from it (adding the potential's and earlier sweeps'
-// margins), otherwise Dp, Dm, osc, M are used as given.  Ends with a barrier.
-__device__ inline void block_window(const SweepArgs& a, const uint64_t* slot, double Dp, double Dm, double osc,
-                                    double M, int* shw)
+// Windows of every axis for the next step, from the statistics in `slot`
+// (recorded by the step's sweep kernels, which have all completed).  Wave w of the block runs
+// one of the four one-sided searches of each axis: the neighbour bound and the
+// oscillation bound on each side; the window is the smaller of the two.
+__device__ inline void next_windows(const WinParams& P, const uint64_t* slot, int* win_out, uint32_t* flags)
 {
-    __shared__ int part[4];
-    __shared__ int caps[4];
+    __shared__ int part[kMaxDim][4];
+    __shared__ int caps[kMaxDim][4];
     const int w = threadIdx.x / kWave;
-    if (a.wfix <= 0 && w < 4) {
-        const int dir = (w < 2) ? 1 : -1;
-        const bool level = (w & 1) != 0;
-        double D;
-        if (slot) {
-            M = stat_get(slot, 6);
+    const double M = stat_get(slot, 6);
+    const double osc0 = stat_get(slot, 7) + stat_get(slot, 8);
+    if (w < 4) {
+        for (int ax = 0; ax < P.ndim; ax++) {
+            if (P.wfix[ax] > 0) continue;
+            const int dir = (w < 2) ? 1 : -1;
+            const bool level = (w & 1) != 0;
+            double D;
             if (level)
-                D = (stat_get(slot, 7) + stat_get(slot, 8)) + a.osc_extra;
+                D = osc0 + P.osc_extra[ax];
             else
-                D = dir > 0 ? stat_get(slot, a.axis) + a.dv_fwd : stat_get(slot, 3 + a.axis) + a.dv_bwd;
-        } else {
-            D = level ? osc : (dir > 0 ? Dp : Dm);
-        }
-        const double sbase = 1.0 + M + a.slack_extra;
-        int64_t est = 0;
-        if (a.fast || a.quad) {
-            // k(dir s) = c s^2 - dir p s with p = 2c pofs
-            const double c = a.cq, p = 2.0 * a.cq * a.pofs * (double)dir;
-            double e;
-            if (level)
-                e = (p + sqrt(fmax(p * p + 4.0 * c * fmax(D, 0.0), 0.0))) / (2.0 * c);
-            else
-                e = (D + p) / (2.0 * c) + 0.5;
-            if (e > 0.0 && e < 1e9) est = (int64_t)e;
-        }
-        bool cap = false;
-        const int r = window_side(a.kin.k, a.kin.kcap, dir, D, sbase, level, est, &cap);
-        if (threadIdx.x % kWave == 0) {
-            part[w] = r;
-            caps[w] = cap ? 1 : 0;
+                D = dir > 0 ? stat_get(slot, ax) + P.dvf[ax] : stat_get(slot, 3 + ax) + P.dvb[ax];
+            const double sbase = 1.0 + M + P.slack_extra;
+            int64_t est = 0;
+            if (P.quad[ax]) {
+                const double c = P.cq[ax], p = 2.0 * P.cq[ax] * P.pofs[ax] * (double)dir;
+                double e;
+                if (level)
+                    e = (p + sqrt(fmax(p * p + 4.0 * c * fmax(D, 0.0), 0.0))) / (2.0 * c);
+                else
+                    e = (D + p) / (2.0 * c) + 0.5;
+                if (e > 0.0 && e < 1e9) est = (int64_t)e;
+            }
+            bool cap = false;
+            const int r = window_side(P.k[ax], P.kcap[ax], dir, D, sbase, level, est, &cap);
+            if (threadIdx.x % kWave == 0) {
+                part[ax][w] = r;
+                caps[ax][w] = cap ? 1 : 0;
+            }
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int wp, wm;
-        bool cap = false;
-        if (a.wfix > 0) {
-            wp = wm = a.wfix;
-        } else {
-            wp = min(part[0], part[1]);
-            wm = min(part[2], part[3]);
-            cap = (caps[0] && caps[1]) || (caps[2] && caps[3]);
+        for (int ax = 0; ax < P.ndim; ax++) {
+            int wp, wm;
+            bool cap = false;
+            if (P.wfix[ax] > 0) {
+                wp = wm = P.wfix[ax];
+            } else {
+                wp = min(part[ax][0], part[ax][1]);
+                wm = min(part[ax][2], part[ax][3]);
+                cap = (caps[ax][0] && caps[ax][1]) || (caps[ax][2] && caps[ax][3]);
+            }
+            win_out[2 * ax] = wp;
+            win_out[2 * ax + 1] = wm;
+            if (cap && P.cap_err[ax]) atomicOr(&flags[0], kErrWindowCap);
+            atomicMax(&flags[kFlagWin + ax * kSpread], (uint32_t)max(wp, wm));
         }
-        shw[0] = wp;
-        shw[1] = wm;
-        if (cap && a.cap_is_error) atomicOr(&a.flags[0], kErrWindowCap);
-        atomicMax(&a.flags[kFlagWin + a.axis * kSpread + (int)(blockIdx.x % kSpread)], (uint32_t)max(wp, wm));
     }
     __syncthreads();
 }

@@ -68,11 +68,12 @@ namespace {
 
 __device__ __forceinline__ unsigned long long kinf() { return enc(INFINITY); }
 
-// ROW: nr whole rows of unit stride per block (window = widest of the rows'
-// own bounds).  TILE: C lines x R targets (+1 extra target for the next
-// step's bound), window from the stats slot, staged before the sources.
+// ROW: nr whole rows of unit stride per block, 256/nr threads per row.
+// TILE: C lines x R targets (+1 extra target for the next step's bound).
 // Staged source p of line l: ROW -> U[l * RS + p], TILE -> U[p * C + l];
 // key of target t of line l: ROW -> WK[l * nt + t], TILE -> WK[t * C + l].
+// Each thread walks a contiguous run of sources of its line, so each u value
+// is read once and each crossing sigma is computed once.
 template <int C, int ROW, int EPI, int ARG>
 __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in, double* __restrict__ out,
                                                   const double* __restrict__ kc, SweepArgs a, ClaimLds L,
@@ -80,19 +81,19 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
 {
     extern __shared__ double sm[];
     __shared__ double red[24];
-    __shared__ int shw[4];
     constexpr double kEps = 1e-6;
-    constexpr int RP = kBlock / C;     // TILE: target rows per pass
     const int H = L.H;
-    const int64_t N = a.g.n, S = a.g.stride;
+    const int N = (int)a.g.n;
+    const int64_t S = a.g.stride;
 
+    // ---- geometry ----
     int64_t r0 = 0, lb;
     int Rt, NT, nrow = 1;
     if (ROW) {
         lb = (int64_t)blockIdx.x * L.nr;
         nrow = (int)min((int64_t)L.nr, a.g.nlines - lb);
-        Rt = (int)N;
-        NT = (int)N;
+        Rt = N;
+        NT = N;
     } else {
         const int R = a.tile_rows;
         const int64_t nTB = (N + R - 1) / R;
@@ -100,160 +101,124 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
         const int64_t b = remap_block(blockIdx.x, nTB * nLB);
         lb = b / nTB;
         r0 = (b % nTB) * R;
-        Rt = (int)min((int64_t)R, N - r0);
+        Rt = (int)min((int64_t)R, (int64_t)N - r0);
         NT = Rt + 1;
     }
-    const int RS = L.RS;
+    // a thread's line and its rank among the threads of that line
+    const int tpl = ROW ? kBlock / L.nr : kBlock / C;         // threads per line
+    const int l = ROW ? (int)threadIdx.x / tpl : (int)threadIdx.x % C;
+    const int lt = ROW ? (int)threadIdx.x % tpl : (int)threadIdx.x / C;
+    int64_t lbase;
+    bool lok;
+    if (ROW) {
+        lok = l < nrow;
+        lbase = (lb + (lok ? l : 0)) * (int64_t)N;
+    } else {
+        const int64_t line = lb * C + l;
+        lok = line < a.g.nlines;
+        const int64_t ln = lok ? line : 0;
+        lbase = (ln % S) + S * N * (ln / S);
+    }
+    const int us = ROW ? 1 : C;                                 // stride of a line's sources in U
     double* U = sm;
     unsigned long long* WK = (unsigned long long*)(sm + (ROW ? (size_t)L.nr * L.RS : (size_t)(L.nt + 2 * H) * C));
     int* AK = (int*)(WK + (size_t)L.nr * L.nt * C);
     double* KT = (double*)(AK + (ARG ? (size_t)L.nr * L.nt * C : 0));
-
-    // TILE: every thread stays on line c = tid % C
-    const int c = threadIdx.x % C, rr = threadIdx.x / C;
-    int64_t tbase = 0;
-    bool tok = true;
-    if (!ROW) {
-        const int64_t line = lb * C + c;
-        tok = line < a.g.nlines;
-        const int64_t ln = tok ? line : 0;
-        tbase = (ln % S) + S * N * (ln / S);
-    }
+    double* Ul = ROW ? U + (size_t)(lok ? l : 0) * L.RS : U + l;
+    unsigned long long* Wl = ROW ? WK + (size_t)(lok ? l : 0) * L.nt : WK + l;
+    int* Al = ROW ? AK + (size_t)(lok ? l : 0) * L.nt : AK + l;
 
     clear_slot(a.stats_clear);
+    int wp, wm;
+    if (a.wfix > 0) {
+        wp = wm = a.wfix;
+    } else {
+        wp = a.win_in[2 * a.axis];
+        wm = a.win_in[2 * a.axis + 1];
+    }
+    wp = __builtin_amdgcn_readfirstlane(wp);
+    wm = __builtin_amdgcn_readfirstlane(wm);
+    const bool staged = wp <= H && wm <= H;
+    const int pA = H - wp, pB = NT - 1 + H + wm;    // sources of all targets of a line
+
+    // ---- stage costs, clear keys, stage sources ----
     const int ktn = 2 * (H + kKtPad) + 1;
     for (int i = threadIdx.x; i < ktn; i += kBlock) {
         const int s = i - (H + kKtPad);
         KT[i] = (s >= -a.kin.kcap && s <= a.kin.kcap) ? kc[s] : INFINITY;
     }
-    if (ROW) {
-        for (int l = 0; l < nrow; l++)
-            for (int t = threadIdx.x; t < NT; t += kBlock) {
-                WK[l * L.nt + t] = kinf();
-                if (ARG) AK[l * L.nt + t] = 0x7fffffff;
-            }
-    } else {
-        for (int t = rr; t < NT; t += RP) {
-            WK[t * C + c] = kinf();
-            if (ARG) AK[t * C + c] = 0x7fffffff;
+    for (int t = lt; t < NT; t += tpl) {
+        Wl[t * us] = kinf();
+        if (ARG) Al[t * us] = 0x7fffffff;
+    }
+    if (lok) {
+        // ROW stages the whole wrapped line [-H, N + H); TILE only the window's sources
+        const int p0 = ROW ? 0 : (staged ? pA : 0), p1 = ROW ? N + 2 * H - 1 : (staged ? pB : -1);
+        int q = (int)((r0 - H + p0 + lt) % N);
+        if (q < 0) q += N;
+        const double* __restrict__ src = in + lbase;
+        for (int p = p0 + lt; p <= p1; p += tpl) {
+            Ul[p * us] = src[S * q];
+            q += tpl;
+            while (q >= N) q -= N;
         }
     }
+    __syncthreads();
 
-    int wp, wm;
-    if (ROW) {
-        const int span = NT + 2 * H;
-        for (int l = 0; l < nrow; l++) {
-            const double* __restrict__ src = in + (lb + l) * N;
-            int q = ((int)threadIdx.x - H) % (int)N;
-            if (q < 0) q += (int)N;
-            for (int p = threadIdx.x; p < span; p += kBlock) {
-                U[l * RS + p] = src[q];
-                q += kBlock;
-                while (q >= N) q -= (int)N;
-            }
-        }
-        __syncthreads();
-        double dp = -INFINITY, dm = -INFINITY, am = 0.0, hi = -INFINITY, nlo = -INFINITY;
-        if (a.wfix <= 0) {
-            for (int l = 0; l < nrow; l++)
-                for (int t = threadIdx.x; t < (int)N; t += kBlock) {
-                    const double x = U[l * RS + H + t], y = U[l * RS + H + t + 1];
-                    dp = fmax(dp, y - x);
-                    dm = fmax(dm, x - y);
-                    am = fmax(am, fabs(x));
-                    hi = fmax(hi, x);
-                    nlo = fmax(nlo, -x);
-                }
-            block_max3(dp, dm, am, red);
-            double t = 0.0;
-            block_max3(hi, nlo, t, red);
-        }
-        block_window(a, nullptr, dp, dm, hi + nlo, am, shw);
-        wp = __builtin_amdgcn_readfirstlane(shw[0]);
-        wm = __builtin_amdgcn_readfirstlane(shw[1]);
-    } else {
-        block_window(a, a.stats_in, 0.0, 0.0, 0.0, 0.0, shw);
-        wp = __builtin_amdgcn_readfirstlane(shw[0]);
-        wm = __builtin_amdgcn_readfirstlane(shw[1]);
-        if (wp <= H && wm <= H) {
-            const int p0 = H - wp, p1 = H + NT - 1 + wm;
-            int64_t q = (r0 - wp + rr) % N;
-            if (q < 0) q += N;
-            const double* __restrict__ src = in + tbase;
-            for (int p = p0 + rr; p <= p1; p += RP) {
-                U[p * C + c] = tok ? src[S * q] : 0.0;
-                q += RP;
-                while (q >= N) q -= N;
-            }
-        }
-        __syncthreads();
-    }
-    const bool staged = wp <= H && wm <= H;
-    const int pA = H - wp, pB = NT - 1 + H + wm;    // sources of all targets of a line
     const int kofs = H + kKtPad;
-
-    // claim of source p of a line: targets (sigma_{p-1}, sigma_p], widened by kEps
-    auto claim = [&](const double* Ul, int ustride, int p, int& tlo, int& thi) {
-        const double up = Ul[p * ustride];
-        const double jl = (double)(p - H);
-        double slo = -INFINITY, shi = INFINITY;
-        if (p > pA) slo = (jl - 0.5) + ((up - Ul[(p - 1) * ustride]) * inv2c + pofs);
-        if (p < pB) shi = (jl + 0.5) + ((Ul[(p + 1) * ustride] - up) * inv2c + pofs);
-        tlo = slo < -1.0 ? 0 : max(0, (int)ceil(slo - kEps));
-        thi = shi > (double)NT ? NT - 1 : min(NT - 1, (int)floor(shi + kEps));
-        return up;
-    };
-
     if (staged) {
+        // ---- claims: source p offers itself to the targets in (sigma_{p-1}, sigma_p] ----
+        const int np = pB - pA + 1;
+        int ch = (np + tpl - 1) / tpl;
+        ch |= 1;   // odd run length: the runs' first sources fall on distinct LDS banks
+        const int q0 = pA + lt * ch, q1 = min(q0 + ch, pB + 1);
         for (int pass = 0; pass < (ARG ? 2 : 1); pass++) {
-            const int nl = ROW ? nrow : 1;
-            for (int l = 0; l < nl; l++) {
-                const double* Ul = ROW ? U + l * RS : U + c;
-                const int us = ROW ? 1 : C;
-                unsigned long long* Wl = ROW ? WK + l * L.nt : WK + c;
-                int* Al = ROW ? AK + l * L.nt : AK + c;
-                const int ws = ROW ? 1 : C;
-                const int step = ROW ? kBlock : RP;
-                for (int p = pA + (ROW ? (int)threadIdx.x : rr); p <= pB; p += step) {
-                    int tlo, thi;
-                    const double up = claim(Ul, us, p, tlo, thi);
+            if (lok && q0 < q1) {
+                double ucur = Ul[q0 * us];
+                double jl = (double)(q0 - H);
+                double slo = -INFINITY;
+                if (q0 > pA) slo = (jl - 0.5) + ((ucur - Ul[(q0 - 1) * us]) * inv2c + pofs);
+                for (int p = q0; p < q1; p++) {
+                    double unext = 0.0, shi = INFINITY;
+                    if (p < pB) {
+                        unext = Ul[(p + 1) * us];
+                        shi = (jl + 0.5) + ((unext - ucur) * inv2c + pofs);
+                    }
+                    const int tlo = slo < -1.0 ? 0 : max(0, (int)ceil(slo - kEps));
+                    const int thi = shi > (double)NT ? NT - 1 : min(NT - 1, (int)floor(shi + kEps));
                     for (int t = tlo; t <= thi; t++) {
                         const int s = t - (p - H);
-                        if (s < -(H + kKtPad) || s > H + kKtPad) continue;
-                        const unsigned long long key = enc(up + KT[s + kofs]);
+                        if ((unsigned)(s + kofs) > (unsigned)(2 * kofs)) continue;
+                        const unsigned long long key = enc(ucur + KT[s + kofs]);
                         if (pass == 0)
-                            atomicMin(&Wl[t * ws], key);
-                        else if (key == Wl[t * ws])
-                            atomicMin(&Al[t * ws], p);
+                            atomicMin(&Wl[t * us], key);
+                        else if (key == Wl[t * us])
+                            atomicMin(&Al[t * us], p);
                     }
+                    slo = shi;
+                    ucur = unext;
+                    jl += 1.0;
                 }
             }
             __syncthreads();
         }
     } else {
-        // ---- fallback: exhaustive window ----
-        const int nl = ROW ? nrow : 1;
-        for (int l = 0; l < nl; l++) {
-            const int step = ROW ? kBlock : RP;
-            for (int t = ROW ? (int)threadIdx.x : rr; t < NT; t += step) {
-                double best = INFINITY;
-                int arg = 0;
-                if (ROW || tok) {
-                    int64_t j = (r0 + t - wp) % N;
-                    if (j < 0) j += N;
-                    for (int e = -wp; e <= wm; ++e) {
-                        const double v = (ROW ? U[l * RS + H + (int)j] : in[tbase + S * j]) + kc[-e];
-                        if (v < best) {
-                            best = v;
-                            arg = e;
-                        }
-                        if (++j == N) j = 0;
-                    }
+        // ---- fallback: exhaustive window (ROW: wrapped staged line, TILE: global) ----
+        for (int t = lt; t < NT && lok; t += tpl) {
+            double best = INFINITY;
+            int arg = 0;
+            int j = (int)((r0 + t - wp) % N);
+            if (j < 0) j += N;
+            for (int e = -wp; e <= wm; ++e) {
+                const double v = (ROW ? Ul[H + j] : in[lbase + S * j]) + kc[-e];
+                if (v < best) {
+                    best = v;
+                    arg = e;
                 }
-                const int k = ROW ? l * L.nt + t : t * C + c;
-                WK[k] = enc(best);
-                if (ARG) AK[k] = t + arg + H;
+                if (++j == N) j = 0;
             }
+            Wl[t * us] = enc(best);
+            if (ARG) Al[t * us] = t + arg + H;
         }
         __syncthreads();
     }
@@ -262,27 +227,24 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
     double sp = -INFINITY, sn = -INFINITY, sa = 0.0, hi = -INFINITY, nlo = -INFINITY;
     int amax = 0;
     bool bad = false;
-    const int nl = ROW ? nrow : 1;
-    for (int l = 0; l < nl; l++) {
-        if (!ROW && !tok) break;
-        const int step = ROW ? kBlock : RP;
-        const int64_t lbase = ROW ? (lb + l) * N : tbase;
-        const int64_t sstride = ROW ? 1 : S;
-        for (int t = ROW ? (int)threadIdx.x : rr; t < Rt; t += step) {
-            const int k = ROW ? l * L.nt + t : t * C + c;
-            const double x = dec(WK[k]);
+    if (lok) {
+        double* __restrict__ dst = out + lbase + S * r0;
+        const double* __restrict__ hv = EPI ? a.hv + lbase + S * r0 : nullptr;
+        int16_t* am = (ARG && a.argmin) ? a.argmin + lbase + S * r0 : nullptr;
+        for (int t = lt; t < Rt; t += tpl) {
+            const double x = dec(Wl[t * us]);
             bad |= !(x < INFINITY);
-            const int64_t idx = lbase + sstride * (r0 + t);
             double z = x;
-            if (EPI) z = x - a.hv[idx];
-            out[idx] = z;
-            if (ARG && a.argmin) {
-                const int e = AK[k] - H - t;
-                a.argmin[idx] = (int16_t)e;
+            if (EPI) z = x - hv[S * t];
+            dst[S * t] = z;
+            if (ARG && am) {
+                const int e = Al[t * us] - H - t;
+                am[S * t] = (int16_t)e;
                 amax = max(amax, abs(e));
             }
-            if (!ROW && a.stats_out) {
-                const double y = dec(WK[k + C]);
+            if (a.stats_out) {
+                // next target: TILE has the extra one, ROW wraps
+                const double y = dec(Wl[(ROW && t + 1 == N ? 0 : t + 1) * us]);
                 sp = fmax(sp, y - x);
                 sn = fmax(sn, x - y);
                 sa = fmax(sa, fabs(x));
@@ -299,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
         amax = (int)wave_max((double)amax);
         if (threadIdx.x % kWave == 0) atomicMax(&a.flags[4 + a.axis], (uint32_t)amax);
     }
-    if (!ROW && a.stats_out) {
+    if (a.stats_out) {
         block_max3(sp, sn, sa, red);
         if (EPI) {
             double t = 0.0;
@@ -346,7 +308,9 @@ ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg)
     if (kind == kKindRow) {
         L.C = 1;
         L.nt = (int)N;
-        L.nr = (N <= 2048 && 2048 % N == 0) ? (int)(2048 / N) : 1;
+        // several short rows per block: a power of two (threads per row = 256 / nr)
+        L.nr = 1;
+        while (L.nr < 32 && (int64_t)L.nr * 2 * N <= 2048) L.nr *= 2;
         L.RS = (int)N + 2 * H + 1;
     } else {
         L.C = 16;

@@ -42,6 +42,23 @@ struct KinTab {
     int64_t kcap;
 };
 
+// What the last block of a time step needs to bound every axis' window for
+// the next step (from the statistics the step's sweeps just recorded).
+struct WinParams {
+    const double* k[kMaxDim];      // kinetic tables, offset to s = 0
+    int64_t kcap[kMaxDim];
+    double dvf[kMaxDim];           // bound on tau*(V(x) - V(x+e_a))
+    double dvb[kMaxDim];           // bound on tau*(V(x+e_a) - V(x))
+    double osc_extra[kMaxDim];     // oscillation growth through the sweeps before axis a
+    double cq[kMaxDim];            // mechanical cost c s^2 - p s: c and p / (2c), for guesses
+    double pofs[kMaxDim];
+    int quad[kMaxDim];
+    int cap_err[kMaxDim];          // a window reaching the table end is an error
+    int wfix[kMaxDim];
+    double slack_extra;
+    int ndim;
+};
+
 // Everything a sweep kernel needs besides the arrays.
 struct SweepArgs {
     AxisGeom g;
@@ -68,13 +85,15 @@ struct SweepArgs {
     double cq;                  // c = dx^2 / (2 tau): k(s) = c s^2 - p s
     double inv2c;               // 1 / (2c)
     double pofs;                // p / (2c) = P tau / dx
+    const int* win_in;          // this step's windows: [2a] = W+, [2a+1] = W- of axis a
 };
 
-constexpr int kKindRow = 0;     // whole line in LDS, unit stride, window from the line itself
-constexpr int kKindTile = 1;    // tile of lines x targets with a halo, window from the stats slot
+constexpr int kKindRow = 0;     // whole lines in LDS, unit stride
+constexpr int kKindTile = 1;    // tile of lines x targets with a halo
 
 // ---- kernel launchers (lo_kernels.hip) ----
 hipError_t launch_clear_slots(uint64_t* stats, hipStream_t s);
+hipError_t launch_windows(const WinParams& P, const uint64_t* slot, int* win_out, uint32_t* flags, hipStream_t s);
 hipError_t launch_stats(const double* u, int ndim, const int64_t* n, uint64_t* slot, hipStream_t s);
 hipError_t launch_synth_hv(const double* basis, const double* coef_dev, int nmodes, int64_t npts,
                            double tau, double* hv, hipStream_t s);

@@ -134,28 +134,13 @@ __global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__
     }
     __syncthreads();
 
-    double dp = -INFINITY, dm = -INFINITY, am = 0.0, hi = -INFINITY, nlo = -INFINITY;
-    if (a.wfix <= 0) {
-        if (rb < nrow) {
-            const double* R = sm + rb * RS;
-            for (int i = lr; i < N; i += lpr) {
-                const double x = R[skew(i + H)], y = R[skew(i + 1 + H)];
-                dp = fmax(dp, y - x);
-                dm = fmax(dm, x - y);
-                am = fmax(am, fabs(x));
-                hi = fmax(hi, x);
-                nlo = fmax(nlo, -x);
-            }
-        }
-        block_max3(dp, dm, am, red);
-        double t = 0.0;
-        block_max3(hi, nlo, t, red);
-    }
-    block_window(a, nullptr, dp, dm, hi + nlo, am, shw);
-    const int wp = __builtin_amdgcn_readfirstlane(shw[0]);
-    const int wm = __builtin_amdgcn_readfirstlane(shw[1]);
+    int wp = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis];
+    int wm = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis + 1];
+    wp = __builtin_amdgcn_readfirstlane(wp);
+    wm = __builtin_amdgcn_readfirstlane(wm);
     const bool inlds = wp <= H && wm <= H;
     int amax = 0;
+    double sp = -INFINITY, sn = -INFINITY, sa = 0.0, shi = -INFINITY, snlo = -INFINITY;
 
     const int per_pass = lpr * kTB;
     for (int i0 = 0; i0 < N; i0 += per_pass) {
@@ -199,9 +184,21 @@ __global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__
         const int cnt = min(per_pass, N - i0);
         for (int t = lr; t < cnt && rb < nrow; t += lpr) {
             const int64_t idx = (row0 + rb) * N + i0 + t;
-            double w = W[skew(t)];
-            if (EPI) w = w - a.hv[idx];
+            const double x = W[skew(t)];
+            double w = x;
+            if (EPI) w = x - a.hv[idx];
             out[idx] = w;
+            if (a.stats_out) {
+                const double y = W[skew(t + 1 == N ? 0 : t + 1)];
+                sp = fmax(sp, y - x);
+                sn = fmax(sn, x - y);
+                sa = fmax(sa, fabs(x));
+                if (EPI) {
+                    sa = fmax(sa, fabs(w));
+                    shi = fmax(shi, w);
+                    snlo = fmax(snlo, -w);
+                }
+            }
             if (ARG) {
                 const int e = A[t];
                 if (a.argmin) record_arg(a, idx, e, amax);
@@ -224,6 +221,22 @@ __global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__
     if (ARG && a.argmin) {
         amax = (int)wave_max((double)amax);
         if (threadIdx.x % kWave == 0) atomicMax(&a.flags[4 + a.axis], (uint32_t)amax);
+    }
+    if (a.stats_out) {
+        block_max3(sp, sn, sa, red);
+        if (EPI) {
+            double t = 0.0;
+            block_max3(shi, snlo, t, red);
+        }
+        if (threadIdx.x == 0) {
+            stat_put(a.stats_out, a.axis, sp);
+            stat_put(a.stats_out, 3 + a.axis, sn);
+            stat_put(a.stats_out, 6, sa);
+            if (EPI) {
+                stat_put(a.stats_out, 7, shi);
+                stat_put(a.stats_out, 8, snlo);
+            }
+        }
     }
 }
 
@@ -263,9 +276,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
     const int64_t base = inner + S * N * outer;
 
     clear_slot(a.stats_clear);
-    block_window(a, a.stats_in, 0.0, 0.0, 0.0, 0.0, shw);
-    const int wp = __builtin_amdgcn_readfirstlane(shw[0]);
-    const int wm = __builtin_amdgcn_readfirstlane(shw[1]);
+    const int wp = __builtin_amdgcn_readfirstlane(a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis]);
+    const int wm = __builtin_amdgcn_readfirstlane(a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis + 1]);
     const bool inlds = wp <= H && wm <= H;
     if (inlds) {
         int64_t q = (r0 - wp + rr) % N;   // source of row p = H - wp + rr
@@ -435,6 +447,12 @@ __global__ __launch_bounds__(kBlock) void k_stats(const double* __restrict__ u, 
     }
 }
 
+// The next step's windows of every axis (one block, after the step's sweeps).
+__global__ __launch_bounds__(kBlock) void k_windows(WinParams P, const uint64_t* slot, int* win_out, uint32_t* flags)
+{
+    next_windows(P, slot, win_out, flags);
+}
+
 // hv = fl(tau * fl(sum_m fl(c_m * phi_m))), summed in m order.
 __global__ __launch_bounds__(kBlock) void k_synth_hv(const double* __restrict__ basis,
                                                      const double* __restrict__ coef, int nmodes,
@@ -543,6 +561,12 @@ size_t row_lds_bytes(int64_t N, int halo)
 }
 
 size_t tile_lds_bytes(int halo) { return sizeof(double) * (size_t)(kTileR + 2 * halo + 1) * kTileC; }
+
+hipError_t launch_windows(const WinParams& P, const uint64_t* slot, int* win_out, uint32_t* flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_windows, dim3(1), dim3(kBlock), 0, s, P, slot, win_out, flags);
+    return hipGetLastError();
+}
 
 hipError_t launch_clear_slots(uint64_t* stats, hipStream_t s)
 {
