@@ -570,9 +570,9 @@ lo_status lo_plan(const lo_desc* desc, const lo_potential* V, lo_plan_t* out)
         p->npts *= desc->n[a];
         p->dx[a] = desc->period[a] / (double)desc->n[a];
     }
-    if (p->npts > (1ll << 34)) {
+    if (p->npts >= (1ll << 31)) {   // kernels address a line with 32-bit offsets
         free_plan(p);
-        return LO_ERR_INVALID;
+        return LO_ERR_UNSUPPORTED;
     }
     lo_status st = build_tables(p);
     if (!st) {

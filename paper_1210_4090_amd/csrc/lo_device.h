@@ -61,6 +61,40 @@ __device__ inline void block_max3(double& a, double& b, double& c, double* red)
     __syncthreads();
 }
 
+// Block-wide max of five values; result in every thread (red: 40 doubles).
+__device__ inline void block_max5(double& a, double& b, double& c, double& d, double& e, double* red)
+{
+    a = wave_max(a);
+    b = wave_max(b);
+    c = wave_max(c);
+    d = wave_max(d);
+    e = wave_max(e);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    const int nw = blockDim.x / kWave;
+    __syncthreads();
+    if (l == 0) {
+        red[w] = a;
+        red[8 + w] = b;
+        red[16 + w] = c;
+        red[24 + w] = d;
+        red[32 + w] = e;
+    }
+    __syncthreads();
+    a = red[0];
+    b = red[8];
+    c = red[16];
+    d = red[24];
+    e = red[32];
+    for (int i = 1; i < nw; i++) {
+        a = fmax(a, red[i]);
+        b = fmax(b, red[8 + i]);
+        c = fmax(c, red[16 + i]);
+        d = fmax(d, red[24 + i]);
+        e = fmax(e, red[32 + i]);
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ void clear_slot(uint64_t* slot)
 {
     if (slot && blockIdx.x == 0)

@@ -58,15 +58,13 @@ __host__ __device__ inline size_t claim_lds_bytes(const ClaimLds& f)
         b += sizeof(double) * (size_t)f.nr * f.RS;                     // sources
     else
         b += sizeof(double) * (size_t)(f.nt + 2 * f.H) * f.C;          // sources
-    b += sizeof(unsigned long long) * (size_t)f.nr * f.nt * f.C;       // keys
+    b += sizeof(double) * (size_t)f.nr * f.nt * f.C;                   // best candidate per target
     if (f.arg) b += sizeof(int) * (size_t)f.nr * f.nt * f.C;          // argmin sources
     b += sizeof(double) * (size_t)(2 * (f.H + kKtPad) + 1);            // staged costs
     return (b + 15) & ~(size_t)15;
 }
 
 namespace {
-
-__device__ __forceinline__ unsigned long long kinf() { return enc(INFINITY); }
 
 // ROW: nr whole rows of unit stride per block, 256/nr threads per row.
 // TILE: C lines x R targets (+1 extra target for the next step's bound).
@@ -80,11 +78,11 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
                                                   double inv2c, double pofs)
 {
     extern __shared__ double sm[];
-    __shared__ double red[24];
+    __shared__ double red[40];
     constexpr double kEps = 1e-6;
     const int H = L.H;
     const int N = (int)a.g.n;
-    const int64_t S = a.g.stride;
+    const int S = (int)a.g.stride;   // line offsets fit 32 bits (the plan caps the grid at 2^31 points)
 
     // ---- geometry ----
     int64_t r0 = 0, lb;
@@ -121,11 +119,11 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
     }
     const int us = ROW ? 1 : C;                                 // stride of a line's sources in U
     double* U = sm;
-    unsigned long long* WK = (unsigned long long*)(sm + (ROW ? (size_t)L.nr * L.RS : (size_t)(L.nt + 2 * H) * C));
+    double* WK = sm + (ROW ? (size_t)L.nr * L.RS : (size_t)(L.nt + 2 * H) * C);
     int* AK = (int*)(WK + (size_t)L.nr * L.nt * C);
     double* KT = (double*)(AK + (ARG ? (size_t)L.nr * L.nt * C : 0));
     double* Ul = ROW ? U + (size_t)(lok ? l : 0) * L.RS : U + l;
-    unsigned long long* Wl = ROW ? WK + (size_t)(lok ? l : 0) * L.nt : WK + l;
+    double* Wl = ROW ? WK + (size_t)(lok ? l : 0) * L.nt : WK + l;
     int* Al = ROW ? AK + (size_t)(lok ? l : 0) * L.nt : AK + l;
 
     clear_slot(a.stats_clear);
@@ -148,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
         KT[i] = (s >= -a.kin.kcap && s <= a.kin.kcap) ? kc[s] : INFINITY;
     }
     for (int t = lt; t < NT; t += tpl) {
-        Wl[t * us] = kinf();
+        Wl[t * us] = INFINITY;
         if (ARG) Al[t * us] = 0x7fffffff;
     }
     if (lok) {
@@ -189,10 +187,10 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
                     for (int t = tlo; t <= thi; t++) {
                         const int s = t - (p - H);
                         if ((unsigned)(s + kofs) > (unsigned)(2 * kofs)) continue;
-                        const unsigned long long key = enc(ucur + KT[s + kofs]);
+                        const double v = ucur + KT[s + kofs];
                         if (pass == 0)
-                            atomicMin(&Wl[t * us], key);
-                        else if (key == Wl[t * us])
+                            atomicMin(&Wl[t * us], v);
+                        else if (v == Wl[t * us])
                             atomicMin(&Al[t * us], p);
                     }
                     slo = shi;
@@ -217,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
                 }
                 if (++j == N) j = 0;
             }
-            Wl[t * us] = enc(best);
+            Wl[t * us] = best;
             if (ARG) Al[t * us] = t + arg + H;
         }
         __syncthreads();
@@ -232,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
         const double* __restrict__ hv = EPI ? a.hv + lbase + S * r0 : nullptr;
         int16_t* am = (ARG && a.argmin) ? a.argmin + lbase + S * r0 : nullptr;
         for (int t = lt; t < Rt; t += tpl) {
-            const double x = dec(Wl[t * us]);
+            const double x = Wl[t * us];
             bad |= !(x < INFINITY);
             double z = x;
             if (EPI) z = x - hv[S * t];
@@ -244,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
             }
             if (a.stats_out) {
                 // next target: TILE has the extra one, ROW wraps
-                const double y = dec(Wl[(ROW && t + 1 == N ? 0 : t + 1) * us]);
+                const double y = Wl[(ROW && t + 1 == N ? 0 : t + 1) * us];
                 sp = fmax(sp, y - x);
                 sn = fmax(sn, x - y);
                 sa = fmax(sa, fabs(x));
@@ -262,11 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
         if (threadIdx.x % kWave == 0) atomicMax(&a.flags[4 + a.axis], (uint32_t)amax);
     }
     if (a.stats_out) {
-        block_max3(sp, sn, sa, red);
-        if (EPI) {
-            double t = 0.0;
-            block_max3(hi, nlo, t, red);
-        }
+        block_max5(sp, sn, sa, hi, nlo, red);
         if (threadIdx.x == 0) {
             stat_put(a.stats_out, a.axis, sp);
             stat_put(a.stats_out, 3 + a.axis, sn);

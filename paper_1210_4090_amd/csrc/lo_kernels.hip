@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__
                                                       int RS)
 {
     extern __shared__ double sm[];
-    __shared__ double red[24];
+    __shared__ double red[40];
     __shared__ int shw[2];
     const int N = (int)a.g.n;
     const int lpr = nr > 1 ? N / kTB : kBlock;          // lanes per row
@@ -223,11 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__
         if (threadIdx.x % kWave == 0) atomicMax(&a.flags[4 + a.axis], (uint32_t)amax);
     }
     if (a.stats_out) {
-        block_max3(sp, sn, sa, red);
-        if (EPI) {
-            double t = 0.0;
-            block_max3(shi, snlo, t, red);
-        }
+        block_max5(sp, sn, sa, shi, snlo, red);
         if (threadIdx.x == 0) {
             stat_put(a.stats_out, a.axis, sp);
             stat_put(a.stats_out, 3 + a.axis, sn);
@@ -255,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
                                                        const double* __restrict__ kc, SweepArgs a)
 {
     extern __shared__ double sm[];
-    __shared__ double red[24];
+    __shared__ double red[40];
     __shared__ int shw[2];
     __shared__ double fv[kTileRP + 1][kTileC];
     constexpr int C = kTileC;
@@ -280,13 +276,14 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
     const int wm = __builtin_amdgcn_readfirstlane(a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis + 1]);
     const bool inlds = wp <= H && wm <= H;
     if (inlds) {
-        int64_t q = (r0 - wp + rr) % N;   // source of row p = H - wp + rr
-        if (q < 0) q += N;
+        int q = (int)((r0 - wp + rr) % N);   // source of row p = H - wp + rr
+        if (q < 0) q += (int)N;
         const double* __restrict__ src = in + base;
+        const int Si = (int)S;
         for (int p = H - wp + rr; p <= H + kTileR + wm; p += kTileRP) {
-            sm[p * C + c] = lv ? src[S * q] : 0.0;
+            sm[p * C + c] = lv ? src[Si * q] : 0.0;
             q += kTileRP;
-            while (q >= N) q -= N;
+            while (q >= (int)N) q -= (int)N;
         }
         __syncthreads();
     }
@@ -381,11 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
                 }
             }
         }
-        block_max3(sp, sn, sa, red);
-        if (EPI) {
-            double t = 0.0;
-            block_max3(hi, nlo, t, red);
-        }
+        block_max5(sp, sn, sa, hi, nlo, red);
         if (threadIdx.x == 0) {
             stat_put(a.stats_out, a.axis, sp);
             stat_put(a.stats_out, 3 + a.axis, sn);
@@ -410,7 +403,7 @@ __global__ void k_clear_slots(uint64_t* stats)
 __global__ __launch_bounds__(kBlock) void k_stats(const double* __restrict__ u, int ndim, int64_t n0,
                                                   int64_t n1, int64_t n2, uint64_t* slot)
 {
-    __shared__ double red[24];
+    __shared__ double red[40];
     const int64_t npts = n0 * n1 * n2;
     double dp[3] = {-INFINITY, -INFINITY, -INFINITY};
     double dm[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -482,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_potential_diffs(const double* __rest
                                                             int64_t n0, int64_t n1, int64_t n2,
                                                             uint64_t* out6)
 {
-    __shared__ double red[24];
+    __shared__ double red[40];
     const int64_t npts = n0 * n1 * n2;
     const int64_t nn[3] = {n0, n1, n2};
     const int64_t st[3] = {1, n0, n0 * n1};
