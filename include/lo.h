@@ -134,7 +134,7 @@ lo_status lo_effective_H(int32_t ninst, const lo_desc* descs, const lo_potential
 /*
  * Adjoint of the N-step map u0 -> u^N = T^N u0 for the plan's static
  * potential.  ckpt: device [ceil(nsteps/ckpt_every)][npts] as written by
- * lo_run(n0 = 0); grad_uT: device [npts] = dL/du^N.  Outputs (each may be
+ * lo_run(n0 = 0), may be NULL when nsteps = 0; grad_uT: device [npts] = dL/du^N.  Outputs (each may be
  * NULL): grad_u0 device [npts] = dL/du0; grad_coef host [nmodes] = dL/dc
  * for a basis potential.  Segments of ckpt_every steps are recomputed from
  * the checkpoints with int16 argmins and the upstream gradient is scattered

@@ -1,0 +1,249 @@
+// Reverse pass of the N-step map of eq. uN.  Each axis sweep of eq. eqconvol
+// is piecewise affine in its input: the derivative of w(x) is 1 at the
+// argmin source of x and 0 elsewhere, so the adjoint of a sweep sends the
+// upstream gradient of every target to its argmin source.  The potential
+// step subtracts tau V pointwise, so it passes the gradient through and
+// contributes -tau * sum_x lambda(x) phi_m(x) to the gradient of a basis
+// coefficient.
+//
+// Scatter as a gather.  With a convex cost and the lowest-offset tie rule the
+// lifted argmin source of target i is nondecreasing in i (the Monge property
+// of k(i - j)), so the targets that choose a given source form one
+// contiguous run.  A block stages the int16 offsets of the targets that can
+// reach its tile of sources (a halo of max |offset| on each side), marks the
+// first and last target of every source's run, and each source sums its run
+// in increasing target order.  No atomics, so the result is deterministic and
+// the additions happen in the order of a sequential loop over the grid.  A
+// line whose staged offsets are not monotone (possible only through rounding
+// near exact ties) is summed by scanning every target within the halo.
+#include <algorithm>
+
+#include "lo_device.h"
+
+namespace lo {
+namespace {
+
+using namespace dev;
+
+constexpr int kMaxLinesPerTile = 16;
+
+__device__ __forceinline__ int floor_div(int x, int n) { return x >= 0 ? x / n : -((n - 1 - x) / n); }
+
+__device__ __forceinline__ int64_t line_base(int64_t ln, int S, int N)
+{
+    return (ln % S) + (int64_t)S * N * (ln / S);
+}
+
+// One tile: C lines x R sources [r0, r0 + R) of the axis, targets
+// [r0 - h, r0 + R + h) staged (span = R + 2h positions, position p is the
+// lifted target r0 - h + p).
+__global__ __launch_bounds__(kBlock) void k_scatter(const int16_t* __restrict__ E, const double* __restrict__ lam,
+                                                    double* __restrict__ out, double* __restrict__ Lam,
+                                                    ScatterArgs a, uint32_t* flags)
+{
+    extern __shared__ int smi[];
+    __shared__ int nonmono[kMaxLinesPerTile];
+    const int N = (int)a.g.n, S = (int)a.g.stride, C = a.C, R = a.R, h = a.h, span = a.span;
+    const int nTB = (N + R - 1) / R;
+    const int64_t G = (int64_t)nTB * ((a.g.nlines + C - 1) / C);
+    const int64_t b = remap_block(blockIdx.x, G);
+    const int64_t lb = b / nTB;
+    const int r0 = (int)(b % nTB) * R;
+    const int Rt = min(R, N - r0);
+    int* first = smi;                              // [C][R] first position of each source's run, -1: none
+    int* last = smi + C * R;                       // [C][R]
+    int16_t* es = (int16_t*)(smi + 2 * C * R);     // [C][span] offsets of the staged targets
+    const bool unit = S == 1;
+    // a thread's line (strided axes: fixed, lines are adjacent in memory) and its step along positions
+    const int cq = unit ? 0 : (int)threadIdx.x % C;
+    const int q0 = unit ? (int)threadIdx.x : (int)threadIdx.x / C;
+    const int Q = unit ? kBlock : kBlock / C;
+    const int c_lo = unit ? 0 : cq, c_hi = unit ? C : cq + 1;
+
+    if (threadIdx.x < kMaxLinesPerTile) nonmono[threadIdx.x] = 0;
+    for (int c = c_lo; c < c_hi; c++)
+        for (int j = q0; j < R; j += Q) first[c * R + j] = -1;
+
+    // stage offsets (targets of lines beyond the grid read as offset 0, which
+    // lands outside every tile's source range only for themselves)
+    const int T0 = r0 - h;                     // lifted target of position 0
+    const int t0r = T0 - floor_div(T0, N) * N; // its residue
+    const int qstep = Q % N;
+    bool bad = false;
+    for (int c = c_lo; c < c_hi; c++) {
+        const int64_t ln = lb * C + c;
+        if (ln >= a.g.nlines) {
+            for (int p = q0; p < span; p += Q) es[c * span + p] = 0;
+            continue;
+        }
+        const int64_t base = line_base(ln, S, N);
+        int t = t0r + q0 % N;
+        if (t >= N) t -= N;
+        for (int p = q0; p < span; p += Q) {
+            const int e = E[base + (int64_t)t * S];
+            bad |= e > h || e < -h;
+            es[c * span + p] = (int16_t)e;
+            t += qstep;
+            if (t >= N) t -= N;
+        }
+    }
+    if (bad) atomicOr(&flags[0], kErrAdjointHalo);
+    __syncthreads();
+
+    // runs: a position heads (ends) its source's run when its predecessor
+    // (successor) has another source; any decrease marks the line non-monotone
+    for (int c = c_lo; c < c_hi; c++) {
+        const int16_t* el = es + c * span;
+        for (int p = q0; p < span; p += Q) {
+            const int sr = p - h + el[p];   // source, relative to r0
+            const int sp = p > 0 ? p - 1 - h + el[p - 1] : INT32_MIN;
+            const int sn = p + 1 < span ? p + 1 - h + el[p + 1] : INT32_MAX;
+            if (sp > sr) nonmono[c] = 1;
+            if (sr >= 0 && sr < Rt) {
+                if (sp != sr) first[c * R + sr] = p;
+                if (sn != sr) last[c * R + sr] = p;
+            }
+        }
+    }
+    __syncthreads();
+
+    for (int c = c_lo; c < c_hi; c++) {
+        const int64_t ln = lb * C + c;
+        if (ln >= a.g.nlines) continue;
+        const int64_t base = line_base(ln, S, N);
+        const int16_t* el = es + c * span;
+        const bool mono = nonmono[c] == 0;
+        for (int j = q0; j < Rt; j += Q) {
+            double acc = 0.0;
+            if (mono) {
+                const int f = first[c * R + j];
+                if (f >= 0) {
+                    const int l = last[c * R + j];
+                    // targets in increasing residue order: when the run crosses a
+                    // multiple of N, the part at or above it comes first
+                    const int Tf = T0 + f;
+                    const int kN = (floor_div(Tf, N) + 1) * N;
+                    const int split = (kN <= T0 + l) ? kN - T0 : f;   // first position of the upper part
+                    int t = kN <= T0 + l ? 0 : Tf - (kN - N);
+                    for (int p = split; p <= l; p++) {
+                        acc = acc + lam[base + (int64_t)t * S];
+                        t++;
+                    }
+                    t = Tf - (kN - N);
+                    for (int p = f; p < split; p++) {
+                        acc = acc + lam[base + (int64_t)t * S];
+                        t++;
+                    }
+                }
+            } else {
+                const int pe = min(j + 2 * h, span - 1);
+                int t = T0 + j - floor_div(T0 + j, N) * N;
+                for (int p = j; p <= pe; p++) {
+                    if (p - h + el[p] == j) acc = acc + lam[base + (int64_t)t * S];
+                    if (++t == N) t = 0;
+                }
+            }
+            const int64_t x = base + (int64_t)(r0 + j) * S;
+            out[x] = acc;
+            if (Lam) Lam[x] = Lam[x] + lam[x];
+        }
+    }
+}
+
+// Deterministic block sum (fixed shuffle pattern, waves combined in order).
+__device__ double block_sum(double v, double* red)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1) v = v + __shfl_xor(v, o, kWave);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if (threadIdx.x % kWave == 0) red[w] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int i = 1; i < (int)blockDim.x / kWave; i++) s = s + red[i];
+    __syncthreads();
+    return s;
+}
+
+// partial[m][b] = sum over block b's chunk of Lam(x) * basis_m(x)
+__global__ __launch_bounds__(kBlock) void k_project(const double* __restrict__ Lam,
+                                                    const double* __restrict__ basis, int M, int64_t npts,
+                                                    int64_t chunk, double* __restrict__ partial)
+{
+    __shared__ double red[kBlock / kWave];
+    const int64_t x0 = (int64_t)blockIdx.x * chunk;
+    const int64_t x1 = min(npts, x0 + chunk);
+    for (int m = 0; m < M; m++) {
+        const double* ph = basis + (int64_t)m * npts;
+        double acc = 0.0;
+        for (int64_t x = x0 + threadIdx.x; x < x1; x += kBlock) acc = acc + Lam[x] * ph[x];
+        acc = block_sum(acc, red);
+        if (threadIdx.x == 0) partial[(int64_t)m * gridDim.x + blockIdx.x] = acc;
+    }
+}
+
+// out[m] = sum_b partial[m][b], one block per mode
+__global__ __launch_bounds__(kBlock) void k_project_sum(const double* __restrict__ partial, int G,
+                                                        double* __restrict__ out)
+{
+    __shared__ double red[kBlock / kWave];
+    const double* row = partial + (int64_t)blockIdx.x * G;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < G; i += kBlock) acc = acc + row[i];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
+}  // namespace
+
+size_t scatter_lds_bytes(int C, int R, int h)
+{
+    return sizeof(int) * 2 * (size_t)C * R + sizeof(int16_t) * (size_t)C * (R + 2 * (size_t)h);
+}
+
+bool scatter_layout(const AxisGeom& g, int h, size_t lds_max, ScatterArgs* a)
+{
+    a->g = g;
+    a->h = h;
+    const int64_t N = g.n;
+    int C, R;
+    if (g.stride == 1) {
+        R = (int)std::min<int64_t>(N, 1024);
+        C = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxLinesPerTile, 1024 / R));
+    } else {
+        R = (int)std::min<int64_t>(N, 128);
+        C = kMaxLinesPerTile;
+    }
+    const size_t budget = std::min<size_t>(lds_max, 64 * 1024);
+    while (scatter_lds_bytes(C, R, h) > budget && C > 1) C /= 2;
+    while (scatter_lds_bytes(C, R, h) > budget && R > 64) R /= 2;
+    if (scatter_lds_bytes(C, R, h) > lds_max) return false;
+    a->C = C;
+    a->R = R;
+    a->span = R + 2 * h;
+    return true;
+}
+
+hipError_t launch_scatter(const int16_t* E, const double* lam, double* out, double* Lam, const ScatterArgs& a,
+                          uint32_t* flags, hipStream_t s)
+{
+    const int64_t G = ((a.g.n + a.R - 1) / a.R) * ((a.g.nlines + a.C - 1) / a.C);
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)G), dim3(kBlock), scatter_lds_bytes(a.C, a.R, a.h), s, E, lam,
+                       out, Lam, a, flags);
+    return hipGetLastError();
+}
+
+int project_blocks(int64_t npts) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (npts + 1023) / 1024)); }
+
+hipError_t launch_project(const double* Lam, const double* basis, int M, int64_t npts, double* partial,
+                          double* out, hipStream_t s)
+{
+    const int G = project_blocks(npts);
+    const int64_t chunk = (npts + G - 1) / G;
+    hipLaunchKernelGGL(k_project, dim3(G), dim3(kBlock), 0, s, Lam, basis, M, npts, chunk, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_project_sum, dim3(M), dim3(kBlock), 0, s, partial, G, out);
+    return hipGetLastError();
+}
+
+}  // namespace lo

@@ -64,6 +64,13 @@ struct lo_plan_s {
     GraphEntry graphs[4];
     uint64_t graph_clock = 0;
     hipStream_t cap_stream = nullptr;
+    // reverse pass work buffers, grown on demand
+    double* bw_u = nullptr;          // recomputed state
+    double* bw_lam[2] = {nullptr, nullptr};
+    double* bw_Lam = nullptr;        // sum over steps of the adjoint of u^{n+1}
+    int16_t* bw_arg = nullptr;       // argmins of one segment [steps][ndim][npts]
+    int64_t bw_arg_steps = 0;
+    double* bw_part = nullptr;       // projection partial sums [nmodes][blocks] + [nmodes]
 };
 
 namespace {
@@ -138,6 +145,12 @@ void free_plan(lo_plan_t p)
     for (auto& g : p->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->bw_u) (void)hipFree(p->bw_u);
+    for (double* l : p->bw_lam)
+        if (l) (void)hipFree(l);
+    if (p->bw_Lam) (void)hipFree(p->bw_Lam);
+    if (p->bw_arg) (void)hipFree(p->bw_arg);
+    if (p->bw_part) (void)hipFree(p->bw_part);
     delete p;
 }
 
@@ -527,6 +540,27 @@ bool graphable(lo_plan_t p) { return !(p->d.flags & LO_FLAG_NO_GRAPH) && !p->tim
 
 constexpr int kGraphSteps = 30;   // multiple of the 3 stats slots
 
+// Work buffers of lo_backward for segments of `steps` steps.
+lo_status backward_buffers(lo_plan_t p, int64_t steps, bool coef)
+{
+    const size_t bytes = sizeof(double) * (size_t)p->npts;
+    lo_status st = LO_OK;
+    if (!p->bw_u) st = alloc((void**)&p->bw_u, bytes);
+    for (int i = 0; i < 2 && !st; i++)
+        if (!p->bw_lam[i]) st = alloc((void**)&p->bw_lam[i], bytes);
+    if (!st && coef && !p->bw_Lam) st = alloc((void**)&p->bw_Lam, bytes);
+    if (!st && coef && !p->bw_part)
+        st = alloc((void**)&p->bw_part, sizeof(double) * (size_t)p->nmodes * (project_blocks(p->npts) + 1));
+    if (!st && steps > p->bw_arg_steps) {
+        if (p->bw_arg) (void)hipFree(p->bw_arg);
+        p->bw_arg = nullptr;
+        p->bw_arg_steps = 0;
+        st = alloc((void**)&p->bw_arg, sizeof(int16_t) * (size_t)steps * p->ndim * p->npts);
+        if (!st) p->bw_arg_steps = steps;
+    }
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -612,6 +646,11 @@ lo_status lo_set_coef(lo_plan_t p, const double* coef)
     if (st) return st;
     HIPCHK(hipDeviceSynchronize());
     fill_winparams(p);
+    // captured steps hold the old margins by value
+    for (auto& g : p->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = lo_plan_s::GraphEntry();
+    }
     return LO_OK;
 }
 
@@ -757,9 +796,94 @@ lo_status lo_effective_H(int32_t, const lo_desc*, const lo_potential*, double, d
     return LO_ERR_UNSUPPORTED;
 }
 
-lo_status lo_backward(lo_plan_t, const double*, int64_t, int64_t, const double*, double*, double*, void*)
+lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t ckpt_every,
+                      const double* grad_uT, double* grad_u0, double* grad_coef, void* stream)
 {
-    return LO_ERR_UNSUPPORTED;
+    if (!p || (!ckpt && nsteps > 0) || !grad_uT || nsteps < 0 || ckpt_every <= 0) return LO_ERR_INVALID;
+    if (grad_coef && (p->nmodes <= 0 || !p->basis)) return LO_ERR_INVALID;
+    if (grad_coef && p->time_dep) return LO_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    lo_status st = backward_buffers(p, std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1)),
+                                    grad_coef != nullptr);
+    if (st) return st;
+    const size_t bytes = sizeof(double) * (size_t)p->npts;
+    int cur = 0;
+    HIPCHK(hipMemcpyAsync(p->bw_lam[cur], grad_uT, bytes, hipMemcpyDeviceToDevice, s));
+    if (grad_coef) HIPCHK(hipMemsetAsync(p->bw_Lam, 0, bytes, s));
+    int dev = 0, lds_max = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return LO_ERR_HIP;
+    uint32_t hf[8] = {0};
+    uint32_t errs = 0;
+    const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+    for (int64_t k = nseg - 1; k >= 0 && !st; k--) {
+        const int64_t n0 = k * ckpt_every, n1 = std::min(nsteps, n0 + ckpt_every);
+        if (k < nseg - 1) {   // errors of the previous segment's reverse sweeps, before the flags reset
+            uint32_t f0 = 0;
+            HIPCHK(hipMemcpyAsync(&f0, p->flags, sizeof(f0), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            errs |= f0;
+        }
+        // recompute the segment from its checkpoint, keeping every sweep's argmins
+        HIPCHK(hipMemcpyAsync(p->bw_u, ckpt + (size_t)k * p->npts, bytes, hipMemcpyDeviceToDevice, s));
+        st = prologue(p, p->bw_u, n0, s);
+        for (int64_t n = n0; n < n1 && !st; n++) {
+            if (n > n0 && (n - n0) % kGraphSteps == 0) st = adapt_from_flags(p, s);
+            if (!st) st = enqueue_step(p, p->bw_u, n, p->bw_arg + (size_t)(n - n0) * p->ndim * p->npts, s);
+        }
+        if (st) break;
+        uint32_t f[kFlagWords];
+        HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(f), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        errs |= f[0];
+        if (f[0] & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrArgRange)) break;
+        for (int a = 0; a < p->ndim; a++) {
+            hf[1 + a] = std::max(hf[1 + a], std::max(p->hflags[1 + a], fold_window(f, a)));
+            hf[4 + a] = std::max(hf[4 + a], f[4 + a]);
+        }
+        // reverse: steps n1-1 .. n0, axes d-1 .. 0; the adjoint of u^{n+1}
+        // enters the potential's gradient before the sweeps are undone
+        ScatterArgs sa[kMaxDim];
+        for (int a = 0; a < p->ndim; a++) {
+            AxisGeom g;
+            g.n = p->n[a];
+            g.stride = 1;
+            for (int b = 0; b < a; b++) g.stride *= p->n[b];
+            g.nlines = p->npts / p->n[a];
+            if (!scatter_layout(g, (int)f[4 + a], (size_t)lds_max, &sa[a])) return LO_ERR_UNSUPPORTED;
+        }
+        for (int64_t n = n1 - 1; n >= n0; n--) {
+            for (int a = p->ndim - 1; a >= 0; a--) {
+                const int16_t* E = p->bw_arg + ((size_t)(n - n0) * p->ndim + a) * p->npts;
+                double* Lam = (grad_coef && a == p->ndim - 1) ? p->bw_Lam : nullptr;
+                HIPCHK(launch_scatter(E, p->bw_lam[cur], p->bw_lam[cur ^ 1], Lam, sa[a], p->flags, s));
+                cur ^= 1;
+            }
+        }
+    }
+    if (!st && grad_u0) HIPCHK(hipMemcpyAsync(grad_u0, p->bw_lam[cur], bytes, hipMemcpyDeviceToDevice, s));
+    if (!st && grad_coef) {
+        const int G = project_blocks(p->npts);
+        double* out = p->bw_part + (size_t)p->nmodes * G;
+        HIPCHK(launch_project(p->bw_Lam, p->basis, p->nmodes, p->npts, p->bw_part, out, s));
+        std::vector<double> acc(p->nmodes);
+        HIPCHK(hipMemcpyAsync(acc.data(), out, sizeof(double) * p->nmodes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int m = 0; m < p->nmodes; m++) grad_coef[m] = -p->d.tau * acc[m];
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    uint32_t f0 = 0;
+    HIPCHK(hipMemcpy(&f0, p->flags, sizeof(f0), hipMemcpyDeviceToHost));
+    errs |= f0;
+    hf[0] = errs;
+    for (int i = 0; i < 8; i++) p->hflags[i] = hf[i];
+    p->have_diag = true;
+    p->had_argmin = true;
+    if (st) return st;
+    if (errs & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrAdjointHalo)) return LO_ERR_WINDOW;
+    if (errs & kErrArgRange) return LO_ERR_UNSUPPORTED;
+    return LO_OK;
 }
 
 }  // extern "C"

@@ -21,6 +21,7 @@ constexpr uint32_t kErrWindowCap = 1u;    // computed window exceeded the kineti
 constexpr uint32_t kErrWindowEdge = 2u;   // fixed window: argmin on the edge
 constexpr uint32_t kErrArgRange = 4u;     // argmin offset does not fit int16
 constexpr uint32_t kErrFastPath = 8u;     // fast kernel left a target without a finite candidate
+constexpr uint32_t kErrAdjointHalo = 16u; // reverse pass met an offset beyond its halo (internal error)
 // flags layout: [0] error bits, [4+a] max |argmin|, and the window used by
 // axis a (max over blocks and steps) spread at [kFlagWin + a * kSpread + j]
 constexpr int kFlagWin = 8;
@@ -109,5 +110,24 @@ size_t fast_lds_for(int kind, int64_t N, int tile_rows, int H);
 void row_layout(int64_t N, int halo, int* nr, int* RS, int* H);
 size_t row_lds_bytes(int64_t N, int halo);
 size_t tile_lds_bytes(int halo);
+
+// Reverse sweep (adjoint scatter) of one axis: tiles of C lines x R sources
+// with a halo of h targets on each side (h >= max |argmin offset|).
+struct ScatterArgs {
+    AxisGeom g;
+    int h;
+    int R;
+    int C;
+    int span;   // R + 2h
+};
+
+// ---- reverse pass (lo_adjoint.hip) ----
+size_t scatter_lds_bytes(int C, int R, int h);
+bool scatter_layout(const AxisGeom& g, int h, size_t lds_max, ScatterArgs* a);
+hipError_t launch_scatter(const int16_t* E, const double* lam, double* out, double* Lam, const ScatterArgs& a,
+                          uint32_t* flags, hipStream_t s);
+int project_blocks(int64_t npts);
+hipError_t launch_project(const double* Lam, const double* basis, int M, int64_t npts, double* partial,
+                          double* out, hipStream_t s);
 
 }  // namespace lo

@@ -150,12 +150,14 @@ class Plan:
     def backward(self, ckpt: torch.Tensor, nsteps: int, ckpt_every: int, grad_uT: torch.Tensor,
                  want_u0: bool = True, want_coef: bool = True, stream=None):
         """Adjoint of the N-step map: returns (grad_u0 tensor or None, grad_coef ndarray or None)."""
-        _dev_f64(ckpt, "ckpt")
+        if ckpt is not None and ckpt.numel() > 0:
+            _dev_f64(ckpt, "ckpt")
+        ckpt_ptr = ckpt.data_ptr() if ckpt is not None and ckpt.numel() > 0 else 0
         _dev_f64(grad_uT, "grad_uT", self.shape)
         gu = torch.empty_like(grad_uT) if want_u0 else None
         gc = np.zeros(max(self.nmodes, 1), dtype=np.float64) if (want_coef and self.nmodes > 0) else None
         check("lo_backward", lib().lo_backward(
-            self._h, ctypes.c_void_p(ckpt.data_ptr()), int(nsteps), int(ckpt_every),
+            self._h, ctypes.c_void_p(ckpt_ptr), int(nsteps), int(ckpt_every),
             ctypes.c_void_p(grad_uT.data_ptr()), ctypes.c_void_p(gu.data_ptr() if gu is not None else 0),
             gc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if gc is not None else None, _stream(stream)))
         return gu, (gc[: self.nmodes] if gc is not None else None)
