@@ -15,6 +15,9 @@ using namespace lo;
 
 struct lo_plan_s {
     lo_desc d;
+    int nb = 1;                  // instances advanced together (batched effective Hamiltonians)
+    std::vector<double> Pb;      // [nb][kMaxDim] rotation vector of each instance
+    double* dpofs = nullptr;     // device [nb][kMaxDim] P tau / dx per instance (nb > 1)
     int ndim = 0;
     int64_t n[kMaxDim] = {1, 1, 1};
     int64_t npts = 0;
@@ -151,6 +154,7 @@ void free_plan(lo_plan_t p)
     if (p->bw_Lam) (void)hipFree(p->bw_Lam);
     if (p->bw_arg) (void)hipFree(p->bw_arg);
     if (p->bw_part) (void)hipFree(p->bw_part);
+    if (p->dpofs) (void)hipFree(p->dpofs);
     delete p;
 }
 
@@ -165,24 +169,32 @@ lo_status build_tables(lo_plan_t p)
             p->user_table[a] = true;
             t.assign(p->d.kstar_tab[a], p->d.kstar_tab[a] + 2 * half + 1);
         } else {
-            // every displacement the window can reach on the lifted line: two periods
+            // every displacement the window can reach on the lifted line: two periods;
+            // instance b of a batch at b * (2 cap + 1)
             const int64_t cap = std::min<int64_t>(32767, std::max<int64_t>(64, 2 * p->n[a]));
             p->kcap[a] = cap;
-            t.resize(2 * cap + 1);
-            for (int64_t s = -cap; s <= cap; s++) t[s + cap] = mech_cost(s, p->dx[a], p->d.tau, p->d.P[a]);
+            t.resize((size_t)p->nb * (2 * cap + 1));
+            for (int b = 0; b < p->nb; b++)
+                for (int64_t s = -cap; s <= cap; s++)
+                    t[(size_t)b * (2 * cap + 1) + s + cap] =
+                        mech_cost(s, p->dx[a], p->d.tau, p->Pb[(size_t)b * kMaxDim + a]);
         }
         // hypothesis (i): discretely convex (differences nondecreasing), finite
-        double mx = 0.0;
+        const size_t len = 2 * (size_t)p->kcap[a] + 1;
+        double mx = 0.0, drop = 0.0;
         for (size_t i = 0; i < t.size(); i++) {
             if (!std::isfinite(t[i])) return LO_ERR_INVALID;
             mx = std::max(mx, fabs(t[i]));
         }
-        for (size_t i = 2; i < t.size(); i++)
-            if (!((t[i] - t[i - 1]) >= (t[i - 1] - t[i - 2]))) return LO_ERR_INVALID;
+        for (size_t b0 = 0; b0 < t.size(); b0 += len) {
+            for (size_t i = b0 + 2; i < b0 + len; i++)
+                if (!((t[i] - t[i - 1]) >= (t[i - 1] - t[i - 2]))) return LO_ERR_INVALID;
+            const double k0 = t[b0 + p->kcap[a]];
+            const double kmin = *std::min_element(t.begin() + b0, t.begin() + b0 + len);
+            drop = std::max(drop, k0 - kmin);
+        }
         p->kmaxabs[a] = mx;
-        const double k0 = t[p->kcap[a]];
-        const double kmin = *std::min_element(t.begin(), t.end());
-        p->kzero_drop[a] = (k0 - kmin) * (1.0 + 0x1p-40) + 0x1p-60;
+        p->kzero_drop[a] = drop * (1.0 + 0x1p-40) + 0x1p-60;
         lo_status st = alloc((void**)&p->dkt[a], sizeof(double) * t.size());
         if (st) return st;
         HIPCHK(hipMemcpy(p->dkt[a], t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
@@ -203,7 +215,7 @@ lo_status add_potential_margins(lo_plan_t p, const double* hv, bool first)
         (void)hipFree(d6);
         return LO_ERR_HIP;
     }
-    if (launch_stats(hv, p->ndim, p->n, (uint64_t*)d6 + 16, nullptr) != hipSuccess) {
+    if (launch_stats(hv, p->ndim, p->n, (uint64_t*)d6 + 16, 1, 0, 0, nullptr) != hipSuccess) {
         (void)hipFree(d6);
         return LO_ERR_HIP;
     }
@@ -368,7 +380,11 @@ void fill_winparams(lo_plan_t p)
         W.quad[a] = p->user_table[a] ? 0 : 1;
         W.cap_err[a] = p->user_table[a] ? 0 : 1;
         W.wfix[a] = p->d.window[a];
+        W.bk[a] = 2 * p->kcap[a] + 1;
     }
+    W.b_stats = (int64_t)kSlots * kSlotStride;
+    W.b_win = 4 * kMaxDim;
+    W.pofs_b = p->nb > 1 ? p->dpofs : nullptr;
 }
 
 // The device's one-sided window search, on the host table (for sizing halos).
@@ -488,6 +504,12 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.stats_out = slot(p, n + 1);
         A.stats_clear = a == 0 ? slot(p, n + 2) : nullptr;
         A.win_in = p->win + (size_t)(((n % 2) + 2) % 2) * 2 * kMaxDim;
+        A.nb = p->nb;
+        A.b_u = p->npts;
+        A.b_k = 2 * p->kcap[a] + 1;
+        A.b_stats = (int64_t)kSlots * kSlotStride;
+        A.b_win = 4 * kMaxDim;
+        A.pofs_b = p->nb > 1 ? p->dpofs : nullptr;
         A.flags = p->flags;
         A.hv = a == p->ndim - 1 ? hv : nullptr;
         A.argmin = argmin ? argmin + (size_t)a * p->npts : nullptr;
@@ -503,19 +525,25 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         if (ev) HIPCHK(hipEventRecord(ev[2 * a + 1], s));
     }
     HIPCHK(launch_windows(p->winp, slot(p, n + 1), p->win + (size_t)((((n + 1) % 2) + 2) % 2) * 2 * kMaxDim,
-                          p->flags, s));
+                          p->flags, p->nb, s));
     if (out[p->ndim - 1] != u)
-        HIPCHK(hipMemcpyAsync(u, out[p->ndim - 1], sizeof(double) * p->npts, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(u, out[p->ndim - 1], sizeof(double) * p->npts * p->nb, hipMemcpyDeviceToDevice, s));
     return LO_OK;
 }
 
 lo_status prologue(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
 {
     HIPCHK(hipMemsetAsync(p->flags, 0, sizeof(uint32_t) * kFlagWords, s));
-    HIPCHK(launch_clear_slots(p->stats, s));
-    HIPCHK(launch_stats(u, p->ndim, p->n, slot(p, n0), s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(launch_clear_slots(p->stats, p->nb, s));
+    HIPCHK(launch_stats(u, p->ndim, p->n, slot(p, n0), p->nb, p->npts, (int64_t)kSlots * kSlotStride, s));
     for (int i = 0; i < 8; i++) p->hflags[i] = 0;
+    if (p->nb > 1) {
+        // every instance's first windows on the device, halos from their maximum
+        HIPCHK(launch_windows(p->winp, slot(p, n0), p->win + (size_t)(((n0 % 2) + 2) % 2) * 2 * kMaxDim, p->flags,
+                              p->nb, s));
+        return adapt_from_flags(p, s);
+    }
+    HIPCHK(hipStreamSynchronize(s));
     return adapt_from_slot(p, n0, s);
 }
 
@@ -561,6 +589,84 @@ lo_status backward_buffers(lo_plan_t p, int64_t steps, bool coef)
     return st;
 }
 
+// A plan for nb instances that share the grid, time step and potential and
+// differ in the rotation vector (Pb: [nb][kMaxDim]); nb > 1 is the batched
+// path of lo_effective_H (mechanical costs only).
+lo_status plan_create(const lo_desc* desc, const lo_potential* V, int nb, const double* Pb, lo_plan_t* out)
+{
+    if (!desc || !out || !Pb || nb < 1) return LO_ERR_INVALID;
+    *out = nullptr;
+    if (desc->ndim < 1 || desc->ndim > kMaxDim) return LO_ERR_INVALID;
+    if (!(desc->tau > 0) || !std::isfinite(desc->tau)) return LO_ERR_INVALID;
+    if (desc->method != LO_BRUTE && desc->method != LO_FAST) return LO_ERR_INVALID;
+    if (nb > 1)
+        for (int a = 0; a < desc->ndim; a++)
+            if (desc->kstar_tab[a]) return LO_ERR_UNSUPPORTED;
+    lo_plan_t p = new (std::nothrow) lo_plan_s();
+    if (!p) return LO_ERR_OOM;
+    p->d = *desc;
+    p->nb = nb;
+    p->Pb.assign((size_t)nb * kMaxDim, 0.0);
+    for (int a = 0; a < desc->ndim; a++) p->d.P[a] = Pb[a];
+    p->ndim = desc->ndim;
+    p->npts = 1;
+    for (int a = 0; a < p->ndim; a++) {
+        if (desc->n[a] < 3 || desc->n[a] > (1ll << 31)) {
+            free_plan(p);
+            return LO_ERR_INVALID;
+        }
+        if (!(desc->period[a] > 0) || !std::isfinite(desc->period[a]) || !std::isfinite(Pb[a]) ||
+            desc->window[a] < 0) {
+            free_plan(p);
+            return LO_ERR_INVALID;
+        }
+        p->n[a] = desc->n[a];
+        p->npts *= desc->n[a];
+        p->dx[a] = desc->period[a] / (double)desc->n[a];
+    }
+    for (int b = 0; b < nb; b++)
+        for (int a = 0; a < p->ndim; a++) {
+            if (!std::isfinite(Pb[(size_t)b * kMaxDim + a])) {
+                free_plan(p);
+                return LO_ERR_INVALID;
+            }
+            p->Pb[(size_t)b * kMaxDim + a] = Pb[(size_t)b * kMaxDim + a];
+        }
+    if (p->npts >= (1ll << 31)) {   // kernels address a line with 32-bit offsets
+        free_plan(p);
+        return LO_ERR_UNSUPPORTED;
+    }
+    lo_status st = build_tables(p);
+    if (!st) {
+        for (int a = 0; a < p->ndim; a++)
+            if (desc->window[a] > 0 && desc->window[a] > p->kcap[a]) st = LO_ERR_INVALID;
+    }
+    if (!st) st = alloc((void**)&p->scratch, sizeof(double) * (size_t)p->npts * nb);
+    if (!st) st = alloc((void**)&p->stats, sizeof(uint64_t) * kSlots * kSlotStride * nb);
+    if (!st) st = alloc((void**)&p->flags, sizeof(uint32_t) * kFlagWords);
+    if (!st) st = alloc((void**)&p->win, sizeof(int) * 4 * kMaxDim * nb);
+    if (!st && hipMemset(p->win, 0, sizeof(int) * 4 * kMaxDim * nb) != hipSuccess) st = LO_ERR_HIP;
+    if (!st && nb > 1) {
+        std::vector<double> po((size_t)nb * kMaxDim, 0.0);
+        for (int b = 0; b < nb; b++)
+            for (int a = 0; a < p->ndim; a++)
+                po[(size_t)b * kMaxDim + a] = p->Pb[(size_t)b * kMaxDim + a] * p->d.tau / p->dx[a];
+        st = alloc((void**)&p->dpofs, sizeof(double) * po.size());
+        if (!st && hipMemcpy(p->dpofs, po.data(), sizeof(double) * po.size(), hipMemcpyHostToDevice) != hipSuccess)
+            st = LO_ERR_HIP;
+    }
+    if (!st) st = setup_potential(p, V);
+    if (st) {
+        free_plan(p);
+        return st;
+    }
+    choose_kernels(p);
+    fill_winparams(p);
+    *out = p;
+    return LO_OK;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -580,53 +686,8 @@ const char* lo_status_string(lo_status s)
 
 lo_status lo_plan(const lo_desc* desc, const lo_potential* V, lo_plan_t* out)
 {
-    if (!desc || !out) return LO_ERR_INVALID;
-    *out = nullptr;
-    if (desc->ndim < 1 || desc->ndim > kMaxDim) return LO_ERR_INVALID;
-    if (!(desc->tau > 0) || !std::isfinite(desc->tau)) return LO_ERR_INVALID;
-    if (desc->method != LO_BRUTE && desc->method != LO_FAST) return LO_ERR_INVALID;
-    lo_plan_t p = new (std::nothrow) lo_plan_s();
-    if (!p) return LO_ERR_OOM;
-    p->d = *desc;
-    p->ndim = desc->ndim;
-    p->npts = 1;
-    for (int a = 0; a < p->ndim; a++) {
-        if (desc->n[a] < 3 || desc->n[a] > (1ll << 31)) {
-            free_plan(p);
-            return LO_ERR_INVALID;
-        }
-        if (!(desc->period[a] > 0) || !std::isfinite(desc->period[a]) || !std::isfinite(desc->P[a]) ||
-            desc->window[a] < 0) {
-            free_plan(p);
-            return LO_ERR_INVALID;
-        }
-        p->n[a] = desc->n[a];
-        p->npts *= desc->n[a];
-        p->dx[a] = desc->period[a] / (double)desc->n[a];
-    }
-    if (p->npts >= (1ll << 31)) {   // kernels address a line with 32-bit offsets
-        free_plan(p);
-        return LO_ERR_UNSUPPORTED;
-    }
-    lo_status st = build_tables(p);
-    if (!st) {
-        for (int a = 0; a < p->ndim; a++)
-            if (desc->window[a] > 0 && desc->window[a] > p->kcap[a]) st = LO_ERR_INVALID;
-    }
-    if (!st) st = alloc((void**)&p->scratch, sizeof(double) * (size_t)p->npts);
-    if (!st) st = alloc((void**)&p->stats, sizeof(uint64_t) * kSlots * kSlotStride);
-    if (!st) st = alloc((void**)&p->flags, sizeof(uint32_t) * kFlagWords);
-    if (!st) st = alloc((void**)&p->win, sizeof(int) * 4 * kMaxDim);
-    if (!st && hipMemset(p->win, 0, sizeof(int) * 4 * kMaxDim) != hipSuccess) st = LO_ERR_HIP;
-    if (!st) st = setup_potential(p, V);
-    if (st) {
-        free_plan(p);
-        return st;
-    }
-    choose_kernels(p);
-    fill_winparams(p);
-    *out = p;
-    return LO_OK;
+    if (!desc) return LO_ERR_INVALID;
+    return plan_create(desc, V, 1, desc->P, out);
 }
 
 lo_status lo_plan_destroy(lo_plan_t p)
@@ -791,9 +852,110 @@ lo_status lo_time_kernels(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, do
     return finish(p, s, false);
 }
 
-lo_status lo_effective_H(int32_t, const lo_desc*, const lo_potential*, double, double*, void*)
+lo_status lo_effective_H(int32_t ninst, const lo_desc* descs, const lo_potential* V, double T, double* hbar_out,
+                         void* stream)
 {
-    return LO_ERR_UNSUPPORTED;
+    if (ninst < 0 || (ninst > 0 && (!descs || !V || !hbar_out))) return LO_ERR_INVALID;
+    if (!(T > 0) || !std::isfinite(T)) return LO_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    // instances sharing everything but P run as one batch: the same grid, time
+    // step, method, windows and potential table
+    struct Group {
+        std::vector<int> idx;
+        int64_t steps = 0, per_unit = 0;
+    };
+    std::vector<std::pair<std::vector<uint8_t>, Group>> groups;
+    for (int i = 0; i < ninst; i++) {
+        const lo_desc& d = descs[i];
+        if (d.ndim < 1 || d.ndim > kMaxDim || !(d.tau > 0) || !std::isfinite(d.tau)) return LO_ERR_INVALID;
+        for (int a = 0; a < d.ndim; a++)
+            if (d.kstar_tab[a]) return LO_ERR_UNSUPPORTED;
+        if (V[i].nmodes != 0 || V[i].tcoef) return LO_ERR_UNSUPPORTED;
+        // (dx, tau) rational with 1/tau an integer: whole time units are whole step counts
+        const double inv = 1.0 / d.tau;
+        const int64_t m = llround(inv);
+        if (m < 1 || fabs((double)m - inv) > 1e-9 * inv) return LO_ERR_INVALID;
+        const int64_t K = llround(T * (double)m);
+        if (K < m || fabs((double)K - T * (double)m) > 1e-9 * T * (double)m) return LO_ERR_INVALID;
+        std::vector<uint8_t> key;
+        auto put = [&](const void* v, size_t nbytes) {
+            const uint8_t* c = (const uint8_t*)v;
+            key.insert(key.end(), c, c + nbytes);
+        };
+        put(&d.ndim, sizeof(d.ndim));
+        put(d.n, sizeof(int64_t) * d.ndim);
+        put(d.period, sizeof(double) * d.ndim);
+        put(&d.tau, sizeof(d.tau));
+        put(d.window, sizeof(int32_t) * d.ndim);
+        put(&d.method, sizeof(d.method));
+        put(&d.flags, sizeof(d.flags));
+        put(&V[i].table, sizeof(V[i].table));
+        put(&K, sizeof(K));
+        Group* g = nullptr;
+        for (auto& e : groups)
+            if (e.first == key) g = &e.second;
+        if (!g) {
+            groups.emplace_back(key, Group());
+            g = &groups.back().second;
+            g->steps = K;
+            g->per_unit = m;
+        }
+        g->idx.push_back(i);
+    }
+    for (auto& e : groups) {
+        Group& g = e.second;
+        const lo_desc& d0 = descs[g.idx[0]];
+        int64_t npts = 1;
+        for (int a = 0; a < d0.ndim; a++) npts *= d0.n[a];
+        // batches of at most ~12 GiB of state (u, the step's scratch, the snapshot)
+        const int64_t cap = std::max<int64_t>(1, ((int64_t)12 << 30) / (24 * std::max<int64_t>(npts, 1)));
+        for (size_t c0 = 0; c0 < g.idx.size(); c0 += (size_t)cap) {
+            const int nb = (int)std::min<size_t>((size_t)cap, g.idx.size() - c0);
+            std::vector<double> Pb((size_t)nb * kMaxDim, 0.0);
+            for (int b = 0; b < nb; b++)
+                for (int a = 0; a < d0.ndim; a++) Pb[(size_t)b * kMaxDim + a] = descs[g.idx[c0 + b]].P[a];
+            lo_plan_t p = nullptr;
+            lo_status st = plan_create(&d0, &V[g.idx[c0]], nb, Pb.data(), &p);
+            if (st) return st;
+            double* u = nullptr;
+            double* snap = nullptr;
+            uint64_t* rng = nullptr;
+            st = alloc((void**)&u, sizeof(double) * (size_t)npts * nb);
+            if (!st) st = alloc((void**)&snap, sizeof(double) * (size_t)npts * nb);
+            if (!st) st = alloc((void**)&rng, sizeof(uint64_t) * 2 * nb);
+            std::vector<uint64_t> h(2 * (size_t)nb, host_enc_neg_inf());
+            if (!st && (hipMemsetAsync(u, 0, sizeof(double) * (size_t)npts * nb, s) != hipSuccess ||
+                        hipMemcpyAsync(rng, h.data(), sizeof(uint64_t) * h.size(), hipMemcpyHostToDevice, s) !=
+                            hipSuccess))
+                st = LO_ERR_HIP;
+            // u0 = 0; u(T - 1) kept, then one more time unit to u(T)
+            if (!st) st = lo_run(p, u, 0, g.steps - g.per_unit, 0, nullptr, s);
+            if (!st && hipMemcpyAsync(snap, u, sizeof(double) * (size_t)npts * nb, hipMemcpyDeviceToDevice, s) !=
+                           hipSuccess)
+                st = LO_ERR_HIP;
+            if (!st) st = lo_run(p, u, g.steps - g.per_unit, g.per_unit, 0, nullptr, s);
+            if (!st && launch_diff_range(u, snap, npts, nb, rng, s) != hipSuccess) st = LO_ERR_HIP;
+            if (!st && (hipMemcpyAsync(h.data(), rng, sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost, s) !=
+                            hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess))
+                st = LO_ERR_HIP;
+            if (!st) {
+                for (int b = 0; b < nb; b++) {
+                    const double dmax = host_dec(h[2 * b]), dmin = -host_dec(h[2 * b + 1]);
+                    double* o = hbar_out + (size_t)g.idx[c0 + b] * 3;
+                    o[0] = -dmax;
+                    o[1] = -(dmax + dmin) * 0.5;
+                    o[2] = -dmin;
+                }
+            }
+            if (u) (void)hipFree(u);
+            if (snap) (void)hipFree(snap);
+            if (rng) (void)hipFree(rng);
+            free_plan(p);
+            if (st) return st;
+        }
+    }
+    return LO_OK;
 }
 
 lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t ckpt_every,

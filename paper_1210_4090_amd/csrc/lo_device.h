@@ -113,6 +113,32 @@ __device__ __forceinline__ double stat_get(const uint64_t* slot, int w)
     return wave_max(dec(slot[w * kSpread + threadIdx.x % kWave]));
 }
 
+// A wave-uniform 64-bit value moved to scalar registers, so that pointers
+// offset by it still qualify for scalar loads.
+__device__ __forceinline__ int64_t uniform64(int64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Batched launches: move a sweep's table, slots, windows and P to instance
+// blockIdx.y; returns the offset of the instance's arrays (b * b_u) and sets
+// *koff to that of its kinetic table.
+__device__ __forceinline__ int64_t batch_shift(SweepArgs& a, int64_t* koff)
+{
+    const int64_t b = blockIdx.y;
+    const int64_t ko = uniform64(b * a.b_k);
+    *koff = ko;
+    a.kin.k += ko;
+    if (a.stats_in) a.stats_in += uniform64(b * a.b_stats);
+    if (a.stats_out) a.stats_out += uniform64(b * a.b_stats);
+    if (a.stats_clear) a.stats_clear += uniform64(b * a.b_stats);
+    a.win_in += uniform64(b * a.b_win);
+    if (a.pofs_b) a.pofs = a.pofs_b[b * kMaxDim + a.axis];
+    return uniform64(b * a.b_u);
+}
+
 __device__ __forceinline__ int64_t remap_block(int64_t b, int64_t G)
 {
     // consecutive tiles of the same lines go to one XCD (blocks are dealt to
@@ -177,11 +203,13 @@ __device__ inline int window_side(const double* __restrict__ k, int64_t kcap, in
     return (int)kcap;
 }
 
-// Windows of every axis for the next step, from the statistics in `slot`
-// (recorded by the step's sweep kernels, which have all completed).  Wave w of the block runs
+// Windows of every axis for the next step of instance `inst` (its kinetic
+// tables at inst * bk[a]), from the statistics in `slot` (recorded by the
+// step's sweep kernels, which have all completed).  Wave w of the block runs
 // one of the four one-sided searches of each axis: the neighbour bound and the
 // oscillation bound on each side; the window is the smaller of the two.
-__device__ inline void next_windows(const WinParams& P, const uint64_t* slot, int* win_out, uint32_t* flags)
+__device__ inline void next_windows(const WinParams& P, int64_t inst, const uint64_t* slot, int* win_out,
+                                    uint32_t* flags)
 {
     __shared__ int part[kMaxDim][4];
     __shared__ int caps[kMaxDim][4];
@@ -201,7 +229,8 @@ __device__ inline void next_windows(const WinParams& P, const uint64_t* slot, in
             const double sbase = 1.0 + M + P.slack_extra;
             int64_t est = 0;
             if (P.quad[ax]) {
-                const double c = P.cq[ax], p = 2.0 * P.cq[ax] * P.pofs[ax] * (double)dir;
+                const double po = P.pofs_b ? P.pofs_b[inst * kMaxDim + ax] : P.pofs[ax];
+                const double c = P.cq[ax], p = 2.0 * P.cq[ax] * po * (double)dir;
                 double e;
                 if (level)
                     e = (p + sqrt(fmax(p * p + 4.0 * c * fmax(D, 0.0), 0.0))) / (2.0 * c);
@@ -210,7 +239,7 @@ __device__ inline void next_windows(const WinParams& P, const uint64_t* slot, in
                 if (e > 0.0 && e < 1e9) est = (int64_t)e;
             }
             bool cap = false;
-            const int r = window_side(P.k[ax], P.kcap[ax], dir, D, sbase, level, est, &cap);
+            const int r = window_side(P.k[ax] + inst * P.bk[ax], P.kcap[ax], dir, D, sbase, level, est, &cap);
             if (threadIdx.x % kWave == 0) {
                 part[ax][w] = r;
                 caps[ax][w] = cap ? 1 : 0;

@@ -80,6 +80,14 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
     extern __shared__ double sm[];
     __shared__ double red[40];
     constexpr double kEps = 1e-6;
+    {
+        int64_t ko;
+        const int64_t uo = batch_shift(a, &ko);
+        in += uo;
+        out += uo;
+        kc += ko;
+        if (a.pofs_b) pofs = a.pofs;
+    }
     const int H = L.H;
     const int N = (int)a.g.n;
     const int S = (int)a.g.stride;   // line offsets fit 32 bits (the plan caps the grid at 2^31 points)
@@ -281,7 +289,7 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
     const bool arg = a.argmin != nullptr;
     const bool epi = a.hv != nullptr;
 #define LO_CLAIM_LAUNCH(E, A)                                                                              \
-    hipLaunchKernelGGL((k_claim<C, ROW, E, A>), dim3((unsigned)grid), dim3(kBlock), lds, s, in, out,       \
+    hipLaunchKernelGGL((k_claim<C, ROW, E, A>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out, \
                        a.kin.k, a, L, inv2c, pofs)
     if (epi) {
         if (arg) LO_CLAIM_LAUNCH(1, 1);

@@ -58,6 +58,12 @@ struct WinParams {
     int wfix[kMaxDim];
     double slack_extra;
     int ndim;
+    // batched plans (one block per instance): instance b's tables, slot and
+    // windows sit at b * bk[a], b * b_stats and b * b_win from instance 0's
+    int64_t bk[kMaxDim];
+    int64_t b_stats;
+    int b_win;
+    const double* pofs_b;          // [nb][kMaxDim] per-instance P tau / dx, nullptr: pofs[]
 };
 
 // Everything a sweep kernel needs besides the arrays.
@@ -87,15 +93,28 @@ struct SweepArgs {
     double inv2c;               // 1 / (2c)
     double pofs;                // p / (2c) = P tau / dx
     const int* win_in;          // this step's windows: [2a] = W+, [2a+1] = W- of axis a
+    // batched launches: blockIdx.y is the instance; its arrays, kinetic
+    // table, stats slots and windows sit at these strides from instance 0's
+    int nb;                     // instances (1: plain plan)
+    int64_t b_u;
+    int64_t b_k;
+    int64_t b_stats;
+    int b_win;
+    const double* pofs_b;       // [nb][kMaxDim] per-instance P tau / dx (nullptr: pofs)
 };
 
 constexpr int kKindRow = 0;     // whole lines in LDS, unit stride
 constexpr int kKindTile = 1;    // tile of lines x targets with a halo
 
 // ---- kernel launchers (lo_kernels.hip) ----
-hipError_t launch_clear_slots(uint64_t* stats, hipStream_t s);
-hipError_t launch_windows(const WinParams& P, const uint64_t* slot, int* win_out, uint32_t* flags, hipStream_t s);
-hipError_t launch_stats(const double* u, int ndim, const int64_t* n, uint64_t* slot, hipStream_t s);
+hipError_t launch_clear_slots(uint64_t* stats, int nb, hipStream_t s);
+hipError_t launch_windows(const WinParams& P, const uint64_t* slot, int* win_out, uint32_t* flags, int nb,
+                          hipStream_t s);
+hipError_t launch_stats(const double* u, int ndim, const int64_t* n, uint64_t* slot, int nb, int64_t b_u,
+                        int64_t b_stats, hipStream_t s);
+// per instance of a batch: [b][0] = enc max(u - snap), [b][1] = enc max(snap - u)
+hipError_t launch_diff_range(const double* u, const double* snap, int64_t npts, int nb, uint64_t* out,
+                             hipStream_t s);
 hipError_t launch_synth_hv(const double* basis, const double* coef_dev, int nmodes, int64_t npts,
                            double tau, double* hv, hipStream_t s);
 hipError_t launch_scale(const double* V, double tau, int64_t npts, double* hv, hipStream_t s);

@@ -113,6 +113,13 @@ __global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__
     extern __shared__ double sm[];
     __shared__ double red[40];
     __shared__ int shw[2];
+    {
+        int64_t ko;
+        const int64_t uo = batch_shift(a, &ko);
+        in += uo;
+        out += uo;
+        kc += ko;
+    }
     const int N = (int)a.g.n;
     const int lpr = nr > 1 ? N / kTB : kBlock;          // lanes per row
     const int rb = threadIdx.x / lpr, lr = threadIdx.x % lpr;
@@ -254,6 +261,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
     __shared__ double red[40];
     __shared__ int shw[2];
     __shared__ double fv[kTileRP + 1][kTileC];
+    {
+        int64_t ko;
+        const int64_t uo = batch_shift(a, &ko);
+        in += uo;
+        out += uo;
+        kc += ko;
+    }
     constexpr int C = kTileC;
     const int64_t N = a.g.n, S = a.g.stride;
     const int H = a.halo;
@@ -394,16 +408,21 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
 // ---------------------------------------------------------------------------
 // Helpers
 // ---------------------------------------------------------------------------
+// one block per instance
 __global__ void k_clear_slots(uint64_t* stats)
 {
-    for (int i = threadIdx.x; i < kSlots * kSlotStride; i += blockDim.x) stats[i] = enc_neg_inf();
+    uint64_t* st = stats + (int64_t)blockIdx.x * kSlots * kSlotStride;
+    for (int i = threadIdx.x; i < kSlots * kSlotStride; i += blockDim.x) st[i] = enc_neg_inf();
 }
 
 // Max forward / backward difference along every axis and max |u| of u.
 __global__ __launch_bounds__(kBlock) void k_stats(const double* __restrict__ u, int ndim, int64_t n0,
-                                                  int64_t n1, int64_t n2, uint64_t* slot)
+                                                  int64_t n1, int64_t n2, uint64_t* slot, int64_t b_u,
+                                                  int64_t b_stats)
 {
     __shared__ double red[40];
+    u += (int64_t)blockIdx.y * b_u;      // instance blockIdx.y of a batch
+    slot += (int64_t)blockIdx.y * b_stats;
     const int64_t npts = n0 * n1 * n2;
     double dp[3] = {-INFINITY, -INFINITY, -INFINITY};
     double dm[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -441,9 +460,34 @@ __global__ __launch_bounds__(kBlock) void k_stats(const double* __restrict__ u, 
 }
 
 // The next step's windows of every axis (one block, after the step's sweeps).
+// one block per instance
 __global__ __launch_bounds__(kBlock) void k_windows(WinParams P, const uint64_t* slot, int* win_out, uint32_t* flags)
 {
-    next_windows(P, slot, win_out, flags);
+    const int64_t b = blockIdx.x;
+    next_windows(P, b, slot + b * P.b_stats, win_out + b * P.b_win, flags);
+}
+
+// max(u - snap) and max(snap - u) of instance blockIdx.y
+__global__ __launch_bounds__(kBlock) void k_diff_range(const double* __restrict__ u,
+                                                       const double* __restrict__ snap, int64_t npts,
+                                                       uint64_t* out)
+{
+    __shared__ double red[40];
+    const int64_t b = blockIdx.y;
+    u += b * npts;
+    snap += b * npts;
+    double hi = -INFINITY, lo = -INFINITY, t = 0.0;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npts;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const double d = u[x] - snap[x];
+        hi = fmax(hi, d);
+        lo = fmax(lo, -d);
+    }
+    block_max3(hi, lo, t, red);
+    if (threadIdx.x == 0) {
+        atomicMax((unsigned long long*)&out[2 * b], (unsigned long long)enc(hi));
+        atomicMax((unsigned long long*)&out[2 * b + 1], (unsigned long long)enc(lo));
+    }
 }
 
 // hv = fl(tau * fl(sum_m fl(c_m * phi_m))), summed in m order.
@@ -517,7 +561,7 @@ hipError_t launch_row(const double* in, double* out, const SweepArgs& a, hipStre
     row_layout(a.g.n, a.halo, &nr, &RS, &H);
     const size_t lds = row_lds_bytes(a.g.n, a.halo);
     const int64_t G = (a.g.nlines + nr - 1) / nr;
-    hipLaunchKernelGGL((k_row_brute<ARG, EPI>), dim3((unsigned)G), dim3(kBlock), lds, s, in, out, a.kin.k, a, H,
+    hipLaunchKernelGGL((k_row_brute<ARG, EPI>), dim3((unsigned)G, a.nb), dim3(kBlock), lds, s, in, out, a.kin.k, a, H,
                        nr, RS);
     return hipGetLastError();
 }
@@ -526,7 +570,7 @@ template <int ARG, int EPI>
 hipError_t launch_tile(const double* in, double* out, const SweepArgs& a, hipStream_t s)
 {
     const int64_t G = ((a.g.n + kTileR - 1) / kTileR) * ((a.g.nlines + kTileC - 1) / kTileC);
-    hipLaunchKernelGGL((k_tile_brute<ARG, EPI>), dim3((unsigned)G), dim3(kBlock), tile_lds_bytes(a.halo), s, in,
+    hipLaunchKernelGGL((k_tile_brute<ARG, EPI>), dim3((unsigned)G, a.nb), dim3(kBlock), tile_lds_bytes(a.halo), s, in,
                        out, a.kin.k, a);
     return hipGetLastError();
 }
@@ -555,22 +599,34 @@ size_t row_lds_bytes(int64_t N, int halo)
 
 size_t tile_lds_bytes(int halo) { return sizeof(double) * (size_t)(kTileR + 2 * halo + 1) * kTileC; }
 
-hipError_t launch_windows(const WinParams& P, const uint64_t* slot, int* win_out, uint32_t* flags, hipStream_t s)
+hipError_t launch_windows(const WinParams& P, const uint64_t* slot, int* win_out, uint32_t* flags, int nb,
+                          hipStream_t s)
 {
-    hipLaunchKernelGGL(k_windows, dim3(1), dim3(kBlock), 0, s, P, slot, win_out, flags);
+    hipLaunchKernelGGL(k_windows, dim3(nb), dim3(kBlock), 0, s, P, slot, win_out, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_clear_slots(uint64_t* stats, hipStream_t s)
+hipError_t launch_clear_slots(uint64_t* stats, int nb, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_clear_slots, dim3(1), dim3(64), 0, s, stats);
+    hipLaunchKernelGGL(k_clear_slots, dim3(nb), dim3(64), 0, s, stats);
     return hipGetLastError();
 }
 
-hipError_t launch_stats(const double* u, int ndim, const int64_t* n, uint64_t* slot, hipStream_t s)
+hipError_t launch_stats(const double* u, int ndim, const int64_t* n, uint64_t* slot, int nb, int64_t b_u,
+                        int64_t b_stats, hipStream_t s)
 {
     const int64_t n0 = n[0], n1 = ndim > 1 ? n[1] : 1, n2 = ndim > 2 ? n[2] : 1;
-    hipLaunchKernelGGL(k_stats, dim3(grid_for(n0 * n1 * n2)), dim3(kBlock), 0, s, u, ndim, n0, n1, n2, slot);
+    int g = grid_for(n0 * n1 * n2);
+    if (nb > 1) g = std::max(1, std::min(g, 8192 / nb));
+    hipLaunchKernelGGL(k_stats, dim3(g, nb), dim3(kBlock), 0, s, u, ndim, n0, n1, n2, slot, b_u, b_stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_range(const double* u, const double* snap, int64_t npts, int nb, uint64_t* out,
+                             hipStream_t s)
+{
+    const int g = std::max(1, std::min(grid_for(npts), 16384 / nb));
+    hipLaunchKernelGGL(k_diff_range, dim3(g, nb), dim3(kBlock), 0, s, u, snap, npts, out);
     return hipGetLastError();
 }
 
