@@ -36,6 +36,35 @@ def sweep_bytes(ndim: int, npts: int):
     return [npts * (16 + (8 if a == ndim - 1 else 0)) for a in range(ndim)]
 
 
+# kernel that sweeps axis a of the 2-D headline workload on the fast path
+FAST_2D_KERNELS = {0: "k_claim<1,1,0,0>", 1: "k_claim<16,0,1,0>"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "claim_sweeps_2d_2048sq_hbm_traffic.txt")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    if kernel is None or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals, srcs, digest = {}, [], None
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("traffic_bytes_per_launch "):
+            k, v = line[len("traffic_bytes_per_launch "):].rsplit(":", 1)
+            vals[k.strip()] = float(v)
+        elif line.startswith("kernel_source_sha256:"):
+            digest = line.split(":", 1)[1].strip()
+        elif line.startswith("kernel_sources:"):
+            srcs = line.split(":", 1)[1].split()
+    h = hashlib.sha256()
+    for f in srcs:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if not srcs or h.hexdigest() != digest:
+        return None
+    return vals.get(kernel)
+
+
 def timed_runs(torch, plan, u0, steps, K, W):
     u = torch.empty_like(u0)
     for _ in range(W):
@@ -150,7 +179,7 @@ def measure_hbar(torch, method, subset=32):
             "subset_speedup_batched": t_loop / t_sub}
 
 
-def cpu_baseline(w, nsteps=3):
+def cpu_baseline(w, nsteps=12):
     from oracle import oracle
     t0 = time.perf_counter()
     oracle.run(w.u0, w.tau, w.P, nsteps, V=w.V)
@@ -184,6 +213,8 @@ def main():
     m = measure_workload(torch, w, args.method, args.steps, args.warmup)
     log("headline: %.4g updates/s, %.2f ms per run, kernels %s ms, windows %s"
         % (m["rate"], m["ms_per_run"], m["kernel_ms"], m["window_max"]))
+    kname = FAST_2D_KERNELS.get(m["dominant_axis"]) if args.method == "fast" else None
+    traffic = measured_traffic(kname)
     out = {
         "metric": "grid-point min-plus updates/sec + HBM GB/s, plain vs batched H̄(P) vs fwd+adjoint",
         "value": m["rate"],
@@ -201,8 +232,8 @@ def main():
                    "time_steps_per_run": w.steps, "method": args.method, "P": list(w.P),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": m["dominant_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": m["dominant_GBs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "axis-%d sweep" % m["dominant_axis"],
+                     "frac": m["dominant_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "axis-%d sweep %s" % (m["dominant_axis"], kname or ""),
                      "algorithmic_bytes_per_launch": m["bytes_per_launch"],
                      "kernel_ms": m["kernel_ms"]},
         "effective_GBs_whole_step": sum(sweep_bytes(w.ndim, w.npts)) * w.steps / (m["ms_per_run"] * 1e-3) / 1e9,
