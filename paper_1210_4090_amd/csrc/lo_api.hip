@@ -16,6 +16,7 @@ using namespace lo;
 struct lo_plan_s {
     lo_desc d;
     int nb = 1;                  // instances advanced together (batched effective Hamiltonians)
+    int grid_cap = 1024;         // blocks of a persistent sweep launch (4 per compute unit)
     std::vector<double> Pb;      // [nb][kMaxDim] rotation vector of each instance
     double* dpofs = nullptr;     // device [nb][kMaxDim] P tau / dx per instance (nb > 1)
     int ndim = 0;
@@ -299,18 +300,24 @@ void choose_kernels(lo_plan_t p)
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         lds_max = 65536;
     (void)hipGetLastError();
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        p->grid_cap = 4 * ncu;
+    (void)hipGetLastError();
     const size_t budget = std::min<size_t>((size_t)lds_max, 64 * 1024);
     const size_t fbudget = std::min<size_t>((size_t)lds_max, 96 * 1024);
     const bool fast = p->d.method == LO_FAST;
     for (int a = 0; a < p->ndim; a++) {
         const int64_t N = p->n[a];
         p->fast[a] = fast && !p->user_table[a];
+        // fast: whole rows of a multiple of 8 points for axis 0, tiles otherwise
         const bool row_ok = a == 0 && N <= 2048 &&
-                            (p->fast[a] ? fast_lds_for(kKindRow, N, 0, 1) <= fbudget
+                            (p->fast[a] ? N % 8 == 0 && fast_lds_for(kKindRow, N, 0, 1) <= fbudget
                                         : row_lds_bytes(N, 8) <= budget);
         if (row_ok) {
             p->kind[a] = kKindRow;
-            int64_t H = std::min<int64_t>(N, p->fast[a] ? 256 : 1024);
+            // the fast row kernel wraps claims once around the row: its cost table stays below N
+            int64_t H = p->fast[a] ? std::min<int64_t>(N - 1, 512) : std::min<int64_t>(N, 1024);
             if (p->fast[a])
                 while (H > 1 && fast_lds_for(kKindRow, N, 0, (int)H) > fbudget) H = H * 7 / 8;
             else
@@ -320,8 +327,8 @@ void choose_kernels(lo_plan_t p)
             p->tile_rows[a] = 0;
         } else {
             p->kind[a] = kKindTile;
-            int R = (int)std::min<int64_t>(N, 128);
-            int H = (int)std::min<int64_t>(N, 256);
+            int R = p->fast[a] ? 128 : (int)std::min<int64_t>(N, 128);
+            int H = (int)std::min<int64_t>(N, p->fast[a] ? 512 : 256);
             if (p->fast[a])
                 while (H > 8 && fast_lds_for(kKindTile, N, R, H) > fbudget) H -= 4;
             else
@@ -504,6 +511,7 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.stats_out = slot(p, n + 1);
         A.stats_clear = a == 0 ? slot(p, n + 2) : nullptr;
         A.win_in = p->win + (size_t)(((n % 2) + 2) % 2) * 2 * kMaxDim;
+        A.grid_cap = p->grid_cap;
         A.nb = p->nb;
         A.b_u = p->npts;
         A.b_k = 2 * p->kcap[a] + 1;

@@ -15,71 +15,165 @@
 // neighbours alone always contains the targets a hull vertex owns.  Hence:
 // every source claims the integer targets in (sigma_{j-1}, sigma_j], widened
 // by 1e-6 against rounding, and each target keeps the smallest candidate
-// fl(u_j + k(t - j)) among its claimants.  Sources that are not hull vertices
-// only add genuine candidates (or claim nothing, where sigma decreases), so
-// the minimum is the minimum over all sources -- no hull needs to be built.
-// (The paper's own fast convolution, Section 4, splits u into convex and
-// concave parts and merges slope sequences; this claim form is what turns
-// the same convexity into independent per-source work for a wavefront.)
+// fl(u_j + k(t - j)) among its claimants (an LDS atomic minimum on doubles).
+// Sources that are not hull vertices only add genuine candidates (or claim
+// nothing, where sigma decreases), so the minimum is the minimum over all
+// sources -- no hull needs to be built.  (The paper's own fast convolution,
+// Section 4, splits u into convex and concave parts and merges slope
+// sequences; this claim form is what turns the same convexity into
+// independent per-source work for a wavefront.)
 //
-// The kept value is a genuine candidate of the definition and equals the
-// exhaustive minimum except where two candidates differ by a few ulps.
-// Ties are broken by a second pass that keeps the lowest claiming source
-// among those attaining the minimum.  Windows beyond the staged halo fall back
-// to the exhaustive window loop.
+// A minimiser lies within the step's window, so claims are clipped to the
+// staged part of the cost table (|t - j| <= KH); a clipped candidate is
+// never the minimum.  The kept value is a genuine candidate of the
+// definition and equals the exhaustive minimum except where two candidates
+// differ by a few ulps.  Ties are broken by a second pass that keeps the
+// smallest offset (lowest lifted source) among the claimants attaining the
+// minimum.  Windows beyond the staged table fall back to the exhaustive loop.
+//
+// Work layout: a thread takes chunks of kCh consecutive sources of one line,
+// loads the kCh + 2 values around them once, and computes every crossing once.
+//  - ROW kernel (axis 0, N a multiple of 8): each thread owns 8 consecutive
+//    points of a row (16-byte loads and stores), keys in LDS in a skewed
+//    layout (x -> x + x/8, so chunk-strided lanes hit distinct banks); claims
+//    wrap around the row, so no halo is read; persistent blocks.
+//  - TILE kernel (strided axes): 16 lines side by side x R targets; sources
+//    come straight from global memory (16 adjacent lines = 128 contiguous
+//    bytes per source), only the keys live in LDS.
 #include "lo_internal.h"
 #include "lo_device.h"
 
 #include <math.h>
+
+#include <algorithm>
 
 namespace lo {
 
 namespace {
 
 using namespace dev;
-constexpr int kKtPad = 4;   // staged kinetic costs cover |s| <= H + kKtPad
+constexpr int kCh = 8;           // sources per chunk
+constexpr int kTileLines = 16;   // TILE: lines side by side
+constexpr int kKeyStride = kTileLines + 1;   // TILE key row stride (doubles)
+constexpr double kEps = 1e-6;    // claim widening, in cells
+
+__device__ __forceinline__ int sk(int x) { return x + (x >> 3); }
 
 }  // namespace
 
-// Layout of the dynamic LDS of the claim kernel.
+// Layout of the dynamic LDS of the claim kernels.
 struct ClaimLds {
     int arg;     // argmin array present
-    int nr;      // lines per block along the sweep (row kernel: whole rows)
-    int C;       // lines side by side (tile kernel: 16)
-    int nt;      // targets per line (tile: R + 1, row: N)
-    int H;       // halo
-    int RS;      // stride of a staged line (row kernel) in doubles
+    int row;     // ROW (1) or TILE (0)
+    int nr;      // ROW: rows per tile
+    int RS;      // ROW: skewed key slots of a tile
+    int NT;      // TILE: targets per line (R + 1)
+    int KH;      // staged cost table covers |s| <= KH
 };
 
 __host__ __device__ inline size_t claim_lds_bytes(const ClaimLds& f)
 {
-    size_t b = 0;
-    if (f.C == 1)
-        b += sizeof(double) * (size_t)f.nr * f.RS;                     // sources
-    else
-        b += sizeof(double) * (size_t)(f.nt + 2 * f.H) * f.C;          // sources
-    b += sizeof(double) * (size_t)f.nr * f.nt * f.C;                   // best candidate per target
-    if (f.arg) b += sizeof(int) * (size_t)f.nr * f.nt * f.C;          // argmin sources
-    b += sizeof(double) * (size_t)(2 * (f.H + kKtPad) + 1);            // staged costs
+    size_t b = sizeof(double) * (size_t)(2 * f.KH + 1);                    // costs
+    if (f.row) {
+        b += sizeof(double) * (size_t)f.RS;                                   // keys
+        if (f.arg) b += sizeof(int) * (size_t)f.RS;                           // argmins
+    } else {
+        b += sizeof(double) * (size_t)f.NT * kKeyStride;                     // keys
+        if (f.arg) b += sizeof(int) * (size_t)f.NT * kKeyStride;
+    }
     return (b + 15) & ~(size_t)15;
 }
 
 namespace {
 
-// ROW: nr whole rows of unit stride per block, 256/nr threads per row.
-// TILE: C lines x R targets (+1 extra target for the next step's bound).
-// Staged source p of line l: ROW -> U[l * RS + p], TILE -> U[p * C + l];
-// key of target t of line l: ROW -> WK[l * nt + t], TILE -> WK[t * C + l].
-// Each thread walks a contiguous run of sources of its line, so each u value
-// is read once and each crossing sigma is computed once.
-template <int C, int ROW, int EPI, int ARG>
-__global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in, double* __restrict__ out,
-                                                  const double* __restrict__ kc, SweepArgs a, ClaimLds L,
-                                                  double inv2c, double pofs)
+// Claims of one chunk: sources p0 .. min(p0 + kCh - 1, plast) (lifted) of one
+// line with uu[k] = u(p0 - 1 + k), k = 0 .. kCh + 1.  Targets are clipped to
+// [tmin, tmax] (lifted) and to |t - p| <= KH; key(t) gives the LDS slot of
+// lifted target t.  PASS 0: atomic minimum of the candidate into W;
+// PASS 1: among the candidates equal to W, atomic minimum of the offset
+// (source - target) into A.
+template <int PASS, typename KeyOf>
+__device__ __forceinline__ void claim_chunk(const double (&uu)[kCh + 2], int p0, int plast, int tmin, int tmax,
+                                            const double* KT, int KH, double inv2c, double pofs, double* W,
+                                            int* A, KeyOf key)
+{
+    // crossing k lies between sources p0 - 1 + k and p0 + k
+    int lo[kCh + 1], hi[kCh + 1];
+    double jh = (double)p0 - 0.5;
+#pragma unroll
+    for (int k = 0; k <= kCh; k++) {
+        const double sg = jh + ((uu[k + 1] - uu[k]) * inv2c + pofs);
+        lo[k] = (int)floor(sg - kEps);   // source p0 + k claims from lo[k] + 1
+        hi[k] = (int)floor(sg + kEps);   // source p0 - 1 + k claims up to hi[k]
+        jh += 1.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kCh; k++) {
+        const int p = p0 + k;
+        if (p > plast) break;
+        const int tlo = max(max(lo[k], p - KH - 1), tmin - 1) + 1;
+        const int thi = min(min(hi[k + 1], p + KH), tmax);
+        const double up = uu[k + 1];
+        for (int t = tlo; t <= thi; t++) {
+            const double v = up + KT[KH + t - p];
+            const int s = key(t);
+            if (PASS == 0)
+                atomicMin(&W[s], v);
+            else if (v == W[s])
+                atomicMin(&A[s], p - t);
+        }
+    }
+}
+
+// Fold the forward differences of a run of outputs into the statistics.
+struct SweepStats {
+    double sp = -INFINITY, sn = -INFINITY, sa = 0.0, hi = -INFINITY, nlo = -INFINITY;
+};
+
+template <int EPI>
+__device__ __forceinline__ void fold_stats(SweepStats& st, double x, double y, double z)
+{
+    const double d = y - x;
+    st.sp = fmax(st.sp, d);
+    st.sn = fmax(st.sn, -d);
+    st.sa = fmax(st.sa, fabs(x));
+    if (EPI) {
+        st.sa = fmax(st.sa, fabs(z));
+        st.hi = fmax(st.hi, z);
+        st.nlo = fmax(st.nlo, -z);
+    }
+}
+
+template <int EPI>
+__device__ __forceinline__ void publish_stats(SweepStats& st, const SweepArgs& a, double* red)
+{
+    if (!a.stats_out) return;
+    block_max5(st.sp, st.sn, st.sa, st.hi, st.nlo, red);
+    if (threadIdx.x == 0) {
+        stat_put(a.stats_out, a.axis, st.sp);
+        stat_put(a.stats_out, 3 + a.axis, st.sn);
+        stat_put(a.stats_out, 6, st.sa);
+        if (EPI) {
+            stat_put(a.stats_out, 7, st.hi);
+            stat_put(a.stats_out, 8, st.nlo);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ROW kernel (axis 0, N a multiple of 8, N <= 2048): a tile is nr whole rows
+// (nr N <= 2048 points); thread (r, j) owns points 8j .. 8j + 7 of row r of
+// the tile: it loads them with 16-byte loads, claims for them as sources and
+// writes them as targets.  Keys live in LDS in the skewed layout; claims wrap
+// around the row.  Persistent: a block walks tiles blockIdx.x, + gridDim.x, ...
+// ---------------------------------------------------------------------------
+template <int EPI, int ARG>
+__global__ __launch_bounds__(kBlock) void k_claim_row(const double* __restrict__ in, double* __restrict__ out,
+                                                      const double* __restrict__ kc, SweepArgs a, ClaimLds L,
+                                                      double inv2c, double pofs)
 {
     extern __shared__ double sm[];
     __shared__ double red[40];
-    constexpr double kEps = 1e-6;
     {
         int64_t ko;
         const int64_t uo = batch_shift(a, &ko);
@@ -88,143 +182,235 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
         kc += ko;
         if (a.pofs_b) pofs = a.pofs;
     }
-    const int H = L.H;
     const int N = (int)a.g.n;
-    const int S = (int)a.g.stride;   // line offsets fit 32 bits (the plan caps the grid at 2^31 points)
-
-    // ---- geometry ----
-    int64_t r0 = 0, lb;
-    int Rt, NT, nrow = 1;
-    if (ROW) {
-        lb = (int64_t)blockIdx.x * L.nr;
-        nrow = (int)min((int64_t)L.nr, a.g.nlines - lb);
-        Rt = N;
-        NT = N;
-    } else {
-        const int R = a.tile_rows;
-        const int64_t nTB = (N + R - 1) / R;
-        const int64_t nLB = (a.g.nlines + C - 1) / C;
-        const int64_t b = remap_block(blockIdx.x, nTB * nLB);
-        lb = b / nTB;
-        r0 = (b % nTB) * R;
-        Rt = (int)min((int64_t)R, (int64_t)N - r0);
-        NT = Rt + 1;
-    }
-    // a thread's line and its rank among the threads of that line
-    const int tpl = ROW ? kBlock / L.nr : kBlock / C;         // threads per line
-    const int l = ROW ? (int)threadIdx.x / tpl : (int)threadIdx.x % C;
-    const int lt = ROW ? (int)threadIdx.x % tpl : (int)threadIdx.x / C;
-    int64_t lbase;
-    bool lok;
-    if (ROW) {
-        lok = l < nrow;
-        lbase = (lb + (lok ? l : 0)) * (int64_t)N;
-    } else {
-        const int64_t line = lb * C + l;
-        lok = line < a.g.nlines;
-        const int64_t ln = lok ? line : 0;
-        lbase = (ln % S) + S * N * (ln / S);
-    }
-    const int us = ROW ? 1 : C;                                 // stride of a line's sources in U
-    double* U = sm;
-    double* WK = sm + (ROW ? (size_t)L.nr * L.RS : (size_t)(L.nt + 2 * H) * C);
-    int* AK = (int*)(WK + (size_t)L.nr * L.nt * C);
-    double* KT = (double*)(AK + (ARG ? (size_t)L.nr * L.nt * C : 0));
-    double* Ul = ROW ? U + (size_t)(lok ? l : 0) * L.RS : U + l;
-    double* Wl = ROW ? WK + (size_t)(lok ? l : 0) * L.nt : WK + l;
-    int* Al = ROW ? AK + (size_t)(lok ? l : 0) * L.nt : AK + l;
+    const int KH = L.KH, nr = L.nr;
+    const int cpr = N >> 3;                       // chunks per row
+    const int r = (int)threadIdx.x / cpr;         // row of this thread within a tile
+    const int p0 = ((int)threadIdx.x - r * cpr) << 3;
+    const bool act = r < nr;
+    const int g0 = r * N + p0;                    // first key of this thread (unskewed)
+    double* KT = sm;
+    double* W = KT + (2 * KH + 1);
+    int* A = (int*)(W + L.RS);
 
     clear_slot(a.stats_clear);
-    int wp, wm;
-    if (a.wfix > 0) {
-        wp = wm = a.wfix;
-    } else {
-        wp = a.win_in[2 * a.axis];
-        wm = a.win_in[2 * a.axis + 1];
-    }
+    int wp = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis];
+    int wm = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis + 1];
     wp = __builtin_amdgcn_readfirstlane(wp);
     wm = __builtin_amdgcn_readfirstlane(wm);
-    const bool staged = wp <= H && wm <= H;
-    const int pA = H - wp, pB = NT - 1 + H + wm;    // sources of all targets of a line
-
-    // ---- stage costs, clear keys, stage sources ----
-    const int ktn = 2 * (H + kKtPad) + 1;
-    for (int i = threadIdx.x; i < ktn; i += kBlock) {
-        const int s = i - (H + kKtPad);
+    for (int i = threadIdx.x; i < 2 * KH + 1; i += kBlock) {
+        const int s = i - KH;
         KT[i] = (s >= -a.kin.kcap && s <= a.kin.kcap) ? kc[s] : INFINITY;
     }
-    for (int t = lt; t < NT; t += tpl) {
-        Wl[t * us] = INFINITY;
-        if (ARG) Al[t * us] = 0x7fffffff;
-    }
-    if (lok) {
-        // ROW stages the whole wrapped line [-H, N + H); TILE only the window's sources
-        const int p0 = ROW ? 0 : (staged ? pA : 0), p1 = ROW ? N + 2 * H - 1 : (staged ? pB : -1);
-        int q = (int)((r0 - H + p0 + lt) % N);
-        if (q < 0) q += N;
-        const double* __restrict__ src = in + lbase;
-        for (int p = p0 + lt; p <= p1; p += tpl) {
-            Ul[p * us] = src[S * q];
-            q += tpl;
-            while (q >= N) q -= N;
-        }
-    }
-    __syncthreads();
+    // claims reach |t - p| <= W + 1 for the minimisers; one wrap needs KH < N
+    const bool fast = wp + 1 <= KH && wm + 1 <= KH && KH < N;
+    const int kbase = r * N;
+    auto key = [N, kbase](int t) { return sk(kbase + (t < 0 ? t + N : (t >= N ? t - N : t))); };
 
-    const int kofs = H + kKtPad;
-    if (staged) {
-        // ---- claims: source p offers itself to the targets in (sigma_{p-1}, sigma_p] ----
-        const int np = pB - pA + 1;
-        int ch = (np + tpl - 1) / tpl;
-        ch |= 1;   // odd run length: the runs' first sources fall on distinct LDS banks
-        const int q0 = pA + lt * ch, q1 = min(q0 + ch, pB + 1);
-        for (int pass = 0; pass < (ARG ? 2 : 1); pass++) {
-            if (lok && q0 < q1) {
-                double ucur = Ul[q0 * us];
-                double jl = (double)(q0 - H);
-                double slo = -INFINITY;
-                if (q0 > pA) slo = (jl - 0.5) + ((ucur - Ul[(q0 - 1) * us]) * inv2c + pofs);
-                for (int p = q0; p < q1; p++) {
-                    double unext = 0.0, shi = INFINITY;
-                    if (p < pB) {
-                        unext = Ul[(p + 1) * us];
-                        shi = (jl + 0.5) + ((unext - ucur) * inv2c + pofs);
+    SweepStats st;
+    int amax = 0;
+    bool bad = false;
+    const int64_t ntiles = (a.g.nlines + nr - 1) / nr;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t row = tile * nr + r;
+        const bool ok = act && row < a.g.nlines;
+        const double* __restrict__ src = in + row * N;
+        double uu[kCh + 2];
+        if (ok) {
+            uu[0] = src[p0 == 0 ? N - 1 : p0 - 1];
+            const double2* s2 = (const double2*)(src + p0);
+#pragma unroll
+            for (int k = 0; k < kCh / 2; k++) {
+                const double2 v = s2[k];
+                uu[1 + 2 * k] = v.x;
+                uu[2 + 2 * k] = v.y;
+            }
+            uu[kCh + 1] = src[p0 + kCh == N ? 0 : p0 + kCh];
+#pragma unroll
+            for (int k = 0; k < kCh; k++) {
+                W[sk(g0 + k)] = INFINITY;
+                if (ARG) A[sk(g0 + k)] = 0x7fffffff;
+            }
+        }
+        __syncthreads();
+        if (fast) {
+            if (ok) claim_chunk<0>(uu, p0, N - 1, -KH, N - 1 + KH, KT, KH, inv2c, pofs, W, A, key);
+            __syncthreads();
+            if (ARG) {
+                if (ok) claim_chunk<1>(uu, p0, N - 1, -KH, N - 1 + KH, KT, KH, inv2c, pofs, W, A, key);
+                __syncthreads();
+            }
+        } else {
+            // exhaustive window over the wrapped row, sources from global memory
+            if (ok) {
+                for (int k = 0; k < kCh; k++) {
+                    const int t = p0 + k;
+                    double best = INFINITY;
+                    int arg = 0;
+                    int j = (t - wp) % N;
+                    if (j < 0) j += N;
+                    for (int e = -wp; e <= wm; ++e) {
+                        const double v = src[j] + kc[-e];
+                        if (v < best) {
+                            best = v;
+                            arg = e;
+                        }
+                        if (++j == N) j = 0;
                     }
-                    const int tlo = slo < -1.0 ? 0 : max(0, (int)ceil(slo - kEps));
-                    const int thi = shi > (double)NT ? NT - 1 : min(NT - 1, (int)floor(shi + kEps));
-                    for (int t = tlo; t <= thi; t++) {
-                        const int s = t - (p - H);
-                        if ((unsigned)(s + kofs) > (unsigned)(2 * kofs)) continue;
-                        const double v = ucur + KT[s + kofs];
-                        if (pass == 0)
-                            atomicMin(&Wl[t * us], v);
-                        else if (v == Wl[t * us])
-                            atomicMin(&Al[t * us], p);
-                    }
-                    slo = shi;
-                    ucur = unext;
-                    jl += 1.0;
+                    W[sk(g0 + k)] = best;
+                    if (ARG) A[sk(g0 + k)] = arg;
                 }
             }
             __syncthreads();
         }
+        if (ok) {
+            double x[kCh + 1];
+#pragma unroll
+            for (int k = 0; k < kCh; k++) x[k] = W[sk(g0 + k)];
+            x[kCh] = W[sk(kbase + (p0 + kCh == N ? 0 : p0 + kCh))];
+            double z[kCh];
+            if (EPI) {
+                const double2* h2 = (const double2*)(a.hv + row * N + p0);
+#pragma unroll
+                for (int k = 0; k < kCh / 2; k++) {
+                    const double2 v = h2[k];
+                    z[2 * k] = x[2 * k] - v.x;
+                    z[2 * k + 1] = x[2 * k + 1] - v.y;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kCh; k++) z[k] = x[k];
+            }
+            double2* d2 = (double2*)(out + row * N + p0);
+#pragma unroll
+            for (int k = 0; k < kCh / 2; k++) d2[k] = make_double2(z[2 * k], z[2 * k + 1]);
+#pragma unroll
+            for (int k = 0; k < kCh; k++) {
+                bad |= !(x[k] < INFINITY);
+                if (a.stats_out) fold_stats<EPI>(st, x[k], x[k + 1], z[k]);
+            }
+            if (ARG && a.argmin) {
+                int16_t* am = a.argmin + row * N + p0;
+#pragma unroll
+                for (int k = 0; k < kCh; k++) {
+                    const int e = A[sk(g0 + k)];
+                    am[k] = (int16_t)e;
+                    amax = max(amax, abs(e));
+                }
+            }
+        }
+        __syncthreads();   // keys are reused by the next tile
+    }
+    if (bad) atomicOr(&a.flags[0], kErrFastPath);
+    if (ARG && a.argmin) {
+        amax = (int)wave_max((double)amax);
+        if (threadIdx.x % kWave == 0) atomicMax(&a.flags[4 + a.axis], (uint32_t)amax);
+    }
+    publish_stats<EPI>(st, a, red);
+}
+
+// ---------------------------------------------------------------------------
+// TILE kernel: 16 lines side by side x R targets [r0, r0 + R) (+ target
+// r0 + R for the forward differences of the output), lines of any stride.
+// ---------------------------------------------------------------------------
+template <int EPI, int ARG>
+__global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict__ in, double* __restrict__ out,
+                                                       const double* __restrict__ kc, SweepArgs a, ClaimLds L,
+                                                       double inv2c, double pofs)
+{
+    extern __shared__ double sm[];
+    __shared__ double red[40];
+    {
+        int64_t ko;
+        const int64_t uo = batch_shift(a, &ko);
+        in += uo;
+        out += uo;
+        kc += ko;
+        if (a.pofs_b) pofs = a.pofs;
+    }
+    constexpr int C = kTileLines;
+    const int N = (int)a.g.n;
+    const int S = (int)a.g.stride;   // line offsets fit 32 bits (the plan caps the grid at 2^31 points)
+    const int R = a.tile_rows;
+    const int KH = L.KH;
+    const int nTB = (N + R - 1) / R;
+    const int64_t nLB = (a.g.nlines + C - 1) / C;
+    const int64_t b = remap_block(blockIdx.x, (int64_t)nTB * nLB);
+    const int64_t lb = b / nTB;
+    const int r0 = (int)(b % nTB) * R;
+    const int Rt = min(R, N - r0);
+    const int NT = Rt + 1;
+
+    const int c = (int)threadIdx.x % C;    // line of this thread
+    const int q = (int)threadIdx.x / C;    // rank among the line's 16 threads
+    const int64_t line = lb * C + c;
+    const bool lok = line < a.g.nlines;
+    const int64_t ln = lok ? line : 0;
+    const int lni = (int)ln;   // line indices fit 32 bits
+    const int64_t lbase = (lni % S) + (int64_t)S * N * (lni / S);
+
+    double* KT = sm;
+    double* W = KT + (2 * KH + 1);
+    int* A = (int*)(W + (size_t)L.NT * kKeyStride);
+
+    clear_slot(a.stats_clear);
+    int wp = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis];
+    int wm = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis + 1];
+    wp = __builtin_amdgcn_readfirstlane(wp);
+    wm = __builtin_amdgcn_readfirstlane(wm);
+
+    for (int i = threadIdx.x; i < 2 * KH + 1; i += kBlock) {
+        const int s = i - KH;
+        KT[i] = (s >= -a.kin.kcap && s <= a.kin.kcap) ? kc[s] : INFINITY;
+    }
+    for (int t = q; t < NT; t += kBlock / C) {
+        W[t * kKeyStride + c] = INFINITY;
+        if (ARG) A[t * kKeyStride + c] = 0x7fffffff;
+    }
+    __syncthreads();
+
+    const double* __restrict__ src = in + lbase;
+    const bool fast = wp + 1 <= KH && wm + 1 <= KH;
+    if (fast) {
+        // sources that can reach the targets: [r0 - wp, r0 + NT - 1 + wm]
+        const int pA = r0 - wp, pB = r0 + NT - 1 + wm;
+        const int nch = (pB - pA + kCh) / kCh;
+        for (int pass = 0; pass < (ARG ? 2 : 1); pass++) {
+            for (int ch = q; ch < nch && lok; ch += kBlock / C) {
+                const int p0 = pA + ch * kCh;
+                double uu[kCh + 2];
+                int r = (p0 - 1) % N;
+                if (r < 0) r += N;
+#pragma unroll
+                for (int k = 0; k < kCh + 2; k++) {
+                    uu[k] = src[(int64_t)S * r];
+                    r = r + 1 == N ? 0 : r + 1;
+                }
+                auto key = [r0](int t) { return (t - r0) * kKeyStride; };
+                if (pass == 0)
+                    claim_chunk<0>(uu, p0, pB, r0, r0 + NT - 1, KT, KH, inv2c, pofs, W + c, A + c, key);
+                else
+                    claim_chunk<1>(uu, p0, pB, r0, r0 + NT - 1, KT, KH, inv2c, pofs, W + c, A + c, key);
+            }
+            __syncthreads();
+        }
     } else {
-        // ---- fallback: exhaustive window (ROW: wrapped staged line, TILE: global) ----
-        for (int t = lt; t < NT && lok; t += tpl) {
+        // exhaustive window straight from global memory
+        for (int t = q; t < NT && lok; t += kBlock / C) {
             double best = INFINITY;
             int arg = 0;
-            int j = (int)((r0 + t - wp) % N);
+            int j = (r0 + t - wp) % N;
             if (j < 0) j += N;
             for (int e = -wp; e <= wm; ++e) {
-                const double v = (ROW ? Ul[H + j] : in[lbase + S * j]) + kc[-e];
+                const double v = src[(int64_t)S * j] + kc[-e];
                 if (v < best) {
                     best = v;
                     arg = e;
                 }
                 if (++j == N) j = 0;
             }
-            Wl[t * us] = best;
-            if (ARG) Al[t * us] = t + arg + H;
+            W[t * kKeyStride + c] = best;
+            if (ARG) A[t * kKeyStride + c] = arg;
         }
         __syncthreads();
     }
@@ -234,23 +420,22 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
     int amax = 0;
     bool bad = false;
     if (lok) {
-        double* __restrict__ dst = out + lbase + S * r0;
-        const double* __restrict__ hv = EPI ? a.hv + lbase + S * r0 : nullptr;
-        int16_t* am = (ARG && a.argmin) ? a.argmin + lbase + S * r0 : nullptr;
-        for (int t = lt; t < Rt; t += tpl) {
-            const double x = Wl[t * us];
+        double* __restrict__ dst = out + lbase + (int64_t)S * r0;
+        const double* __restrict__ hv = EPI ? a.hv + lbase + (int64_t)S * r0 : nullptr;
+        int16_t* am = (ARG && a.argmin) ? a.argmin + lbase + (int64_t)S * r0 : nullptr;
+        for (int t = q; t < Rt; t += kBlock / C) {
+            const double x = W[t * kKeyStride + c];
             bad |= !(x < INFINITY);
             double z = x;
             if (EPI) z = x - hv[S * t];
             dst[S * t] = z;
             if (ARG && am) {
-                const int e = Al[t * us] - H - t;
+                const int e = A[t * kKeyStride + c];
                 am[S * t] = (int16_t)e;
                 amax = max(amax, abs(e));
             }
             if (a.stats_out) {
-                // next target: TILE has the extra one, ROW wraps
-                const double y = Wl[(ROW && t + 1 == N ? 0 : t + 1) * us];
+                const double y = W[(t + 1) * kKeyStride + c];
                 sp = fmax(sp, y - x);
                 sn = fmax(sn, x - y);
                 sa = fmax(sa, fabs(x));
@@ -281,53 +466,62 @@ __global__ __launch_bounds__(kBlock) void k_claim(const double* __restrict__ in,
     }
 }
 
-template <int C, int ROW>
+ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg)
+{
+    ClaimLds L;
+    L.arg = arg ? 1 : 0;
+    L.KH = H;
+    if (kind == kKindRow) {
+        L.row = 1;
+        L.nr = (int)std::max<int64_t>(1, 2048 / N);   // whole rows, at most 2048 points per tile
+        const int g = L.nr * (int)N;
+        L.RS = g + (g >> 3) + 1;                     // skewed keys
+        L.NT = 0;
+    } else {
+        L.row = 0;
+        L.nr = 1;
+        L.RS = 0;
+        L.NT = tile_rows + 1;
+    }
+    return L;
+}
+
+template <int ROW>
 hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, const ClaimLds& L, double inv2c,
                           double pofs, int64_t grid, hipStream_t s)
 {
     const size_t lds = claim_lds_bytes(L);
     const bool arg = a.argmin != nullptr;
     const bool epi = a.hv != nullptr;
-#define LO_CLAIM_LAUNCH(E, A)                                                                              \
-    hipLaunchKernelGGL((k_claim<C, ROW, E, A>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out, \
-                       a.kin.k, a, L, inv2c, pofs)
-    if (epi) {
-        if (arg) LO_CLAIM_LAUNCH(1, 1);
-        else LO_CLAIM_LAUNCH(1, 0);
+#define LO_CLAIM_LAUNCH(K, E, A)                                                                             \
+    hipLaunchKernelGGL((K<E, A>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out, a.kin.k, a, L, \
+                       inv2c, pofs)
+    if (ROW) {
+        if (epi) {
+            if (arg) LO_CLAIM_LAUNCH(k_claim_row, 1, 1);
+            else LO_CLAIM_LAUNCH(k_claim_row, 1, 0);
+        } else {
+            if (arg) LO_CLAIM_LAUNCH(k_claim_row, 0, 1);
+            else LO_CLAIM_LAUNCH(k_claim_row, 0, 0);
+        }
     } else {
-        if (arg) LO_CLAIM_LAUNCH(0, 1);
-        else LO_CLAIM_LAUNCH(0, 0);
+        if (epi) {
+            if (arg) LO_CLAIM_LAUNCH(k_claim_tile, 1, 1);
+            else LO_CLAIM_LAUNCH(k_claim_tile, 1, 0);
+        } else {
+            if (arg) LO_CLAIM_LAUNCH(k_claim_tile, 0, 1);
+            else LO_CLAIM_LAUNCH(k_claim_tile, 0, 0);
+        }
     }
 #undef LO_CLAIM_LAUNCH
     return hipGetLastError();
-}
-
-ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg)
-{
-    ClaimLds L;
-    L.arg = arg ? 1 : 0;
-    L.H = H;
-    if (kind == kKindRow) {
-        L.C = 1;
-        L.nt = (int)N;
-        // several short rows per block: a power of two (threads per row = 256 / nr)
-        L.nr = 1;
-        while (L.nr < 32 && (int64_t)L.nr * 2 * N <= 2048) L.nr *= 2;
-        L.RS = (int)N + 2 * H + 1;
-    } else {
-        L.C = 16;
-        L.nt = tile_rows + 1;
-        L.nr = 1;
-        L.RS = 0;
-    }
-    return L;
 }
 
 }  // namespace
 
 size_t fast_lds_for(int kind, int64_t N, int tile_rows, int H)
 {
-    return claim_lds_bytes(claim_layout(kind, N, tile_rows, H, false));
+    return claim_lds_bytes(claim_layout(kind, N, tile_rows, H, true));
 }
 
 hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double cq, double inv2c, double pofs,
@@ -335,10 +529,14 @@ hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double
 {
     (void)cq;
     const ClaimLds L = claim_layout(a.kind, a.g.n, a.tile_rows, a.halo, a.argmin != nullptr);
-    if (a.kind == kKindRow)
-        return launch_claim_t<1, 1>(in, out, a, L, inv2c, pofs, (a.g.nlines + L.nr - 1) / L.nr, s);
-    const int64_t G = ((a.g.n + a.tile_rows - 1) / a.tile_rows) * ((a.g.nlines + 15) / 16);
-    return launch_claim_t<16, 0>(in, out, a, L, inv2c, pofs, G, s);
+    // ROW: persistent blocks, at most grid_cap along x, each walks several tiles
+    const int64_t cap = std::max(1, a.grid_cap);
+    if (a.kind == kKindRow) {
+        const int64_t tiles = (a.g.nlines + L.nr - 1) / L.nr;
+        return launch_claim_t<1>(in, out, a, L, inv2c, pofs, std::min(tiles, cap), s);
+    }
+    const int64_t tiles = ((a.g.n + a.tile_rows - 1) / a.tile_rows) * ((a.g.nlines + kTileLines - 1) / kTileLines);
+    return launch_claim_t<0>(in, out, a, L, inv2c, pofs, tiles, s);
 }
 
 }  // namespace lo

@@ -95,6 +95,7 @@ struct SweepArgs {
     const int* win_in;          // this step's windows: [2a] = W+, [2a+1] = W- of axis a
     // batched launches: blockIdx.y is the instance; its arrays, kinetic
     // table, stats slots and windows sit at these strides from instance 0's
+    int grid_cap;               // persistent kernels: at most this many blocks along x
     int nb;                     // instances (1: plain plan)
     int64_t b_u;
     int64_t b_k;
