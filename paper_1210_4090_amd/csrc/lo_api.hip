@@ -327,7 +327,7 @@ void choose_kernels(lo_plan_t p)
             p->tile_rows[a] = 0;
         } else {
             p->kind[a] = kKindTile;
-            int R = p->fast[a] ? 128 : (int)std::min<int64_t>(N, 128);
+            int R = p->fast[a] ? 256 : (int)std::min<int64_t>(N, 128);
             int H = (int)std::min<int64_t>(N, p->fast[a] ? 512 : 256);
             if (p->fast[a])
                 while (H > 8 && fast_lds_for(kKindTile, N, R, H) > fbudget) H -= 4;
@@ -410,7 +410,11 @@ int choose_halo(lo_plan_t p, int a, int W)
     if (p->d.window[a] > 0) W = p->d.window[a];
     int H = W + std::max(16, W / 8);
     H = (H + 7) / 8 * 8;
-    return std::max(8, std::min(H, p->halo_max[a]));
+    H = std::max(8, std::min(H, p->halo_max[a]));
+    // fast tiles: longer tiles when the window's halo is wide (fewer halo
+    // sources per target), shorter ones keep more blocks resident otherwise
+    if (p->fast[a] && p->kind[a] == kKindTile) p->tile_rows[a] = H >= 40 ? 256 : 128;
+    return H;
 }
 
 // Windows of step n0 from the statistics of u in stats slot n0 (the same
