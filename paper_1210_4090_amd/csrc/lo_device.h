@@ -95,6 +95,65 @@ __device__ inline void block_max5(double& a, double& b, double& c, double& d, do
     __syncthreads();
 }
 
+// One DPP move of a double (both halves with the same control); lanes without
+// a source keep their own value.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)b, hi = (int)(b >> 32);
+    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false);
+    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)h2 << 32) | (unsigned)l2));
+}
+
+// Wave maximum through row shifts and row broadcasts; valid in lane 63 only.
+__device__ __forceinline__ double wave_max_to63(double v)
+{
+    v = fmax(v, dpp_move<0x111, 0xf>(v));   // row_shr:1
+    v = fmax(v, dpp_move<0x112, 0xf>(v));   // row_shr:2
+    v = fmax(v, dpp_move<0x114, 0xf>(v));   // row_shr:4
+    v = fmax(v, dpp_move<0x118, 0xf>(v));   // row_shr:8  -> lane 15 of each row: row max
+    v = fmax(v, dpp_move<0x142, 0xa>(v));   // row_bcast:15 into rows 1, 3
+    v = fmax(v, dpp_move<0x143, 0xc>(v));   // row_bcast:31 into rows 2, 3 -> lane 63: wave max
+    return v;
+}
+
+// Block-wide max of five values, valid in thread 0 only (red: 40 doubles).
+__device__ inline void block_max5_to0(double& a, double& b, double& c, double& d, double& e, double* red)
+{
+    a = wave_max_to63(a);
+    b = wave_max_to63(b);
+    c = wave_max_to63(c);
+    d = wave_max_to63(d);
+    e = wave_max_to63(e);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    const int nw = blockDim.x / kWave;
+    __syncthreads();
+    if (l == kWave - 1) {
+        red[w] = a;
+        red[8 + w] = b;
+        red[16 + w] = c;
+        red[24 + w] = d;
+        red[32 + w] = e;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = red[0];
+        b = red[8];
+        c = red[16];
+        d = red[24];
+        e = red[32];
+        for (int i = 1; i < nw; i++) {
+            a = fmax(a, red[i]);
+            b = fmax(b, red[8 + i]);
+            c = fmax(c, red[16 + i]);
+            d = fmax(d, red[24 + i]);
+            e = fmax(e, red[32 + i]);
+        }
+    }
+}
+
 __device__ __forceinline__ void clear_slot(uint64_t* slot)
 {
     if (slot && blockIdx.x == 0)

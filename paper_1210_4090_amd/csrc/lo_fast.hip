@@ -148,7 +148,7 @@ template <int EPI>
 __device__ __forceinline__ void publish_stats(SweepStats& st, const SweepArgs& a, double* red)
 {
     if (!a.stats_out) return;
-    block_max5(st.sp, st.sn, st.sa, st.hi, st.nlo, red);
+    block_max5_to0(st.sp, st.sn, st.sa, st.hi, st.nlo, red);
     if (threadIdx.x == 0) {
         stat_put(a.stats_out, a.axis, st.sp);
         stat_put(a.stats_out, 3 + a.axis, st.sn);
@@ -333,21 +333,21 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
     const int S = (int)a.g.stride;   // line offsets fit 32 bits (the plan caps the grid at 2^31 points)
     const int R = a.tile_rows;
     const int KH = L.KH;
+    // block, tile and line indices fit 32 bits (the plan caps the grid at 2^31 points)
     const int nTB = (N + R - 1) / R;
-    const int64_t nLB = (a.g.nlines + C - 1) / C;
-    const int64_t b = remap_block(blockIdx.x, (int64_t)nTB * nLB);
-    const int64_t lb = b / nTB;
-    const int r0 = (int)(b % nTB) * R;
+    const int nLB = (int)((a.g.nlines + C - 1) / C);
+    const int b = (int)remap_block(blockIdx.x, (int64_t)nTB * nLB);
+    const int lb = b / nTB;
+    const int r0 = (b - lb * nTB) * R;
     const int Rt = min(R, N - r0);
     const int NT = Rt + 1;
 
     const int c = (int)threadIdx.x % C;    // line of this thread
     const int q = (int)threadIdx.x / C;    // rank among the line's 16 threads
-    const int64_t line = lb * C + c;
+    const int line = lb * C + c;
     const bool lok = line < a.g.nlines;
-    const int64_t ln = lok ? line : 0;
-    const int lni = (int)ln;   // line indices fit 32 bits
-    const int64_t lbase = (lni % S) + (int64_t)S * N * (lni / S);
+    const int ln = lok ? line : 0;
+    const int64_t lbase = (ln % S) + (int64_t)S * N * (ln / S);
 
     double* KT = sm;
     double* W = KT + (2 * KH + 1);
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
                 if (r < 0) r += N;
 #pragma unroll
                 for (int k = 0; k < kCh + 2; k++) {
-                    uu[k] = src[(int64_t)S * r];
+                    uu[k] = src[S * r];
                     r = r + 1 == N ? 0 : r + 1;
                 }
                 auto key = [r0](int t) { return (t - r0) * kKeyStride; };
@@ -416,35 +416,26 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
     }
 
     // ---- outputs, argmins, stats of this sweep's result ----
-    double sp = -INFINITY, sn = -INFINITY, sa = 0.0, hi = -INFINITY, nlo = -INFINITY;
+    SweepStats st;
     int amax = 0;
     bool bad = false;
     if (lok) {
         double* __restrict__ dst = out + lbase + (int64_t)S * r0;
         const double* __restrict__ hv = EPI ? a.hv + lbase + (int64_t)S * r0 : nullptr;
         int16_t* am = (ARG && a.argmin) ? a.argmin + lbase + (int64_t)S * r0 : nullptr;
+        int off = S * q;
         for (int t = q; t < Rt; t += kBlock / C) {
             const double x = W[t * kKeyStride + c];
             bad |= !(x < INFINITY);
-            double z = x;
-            if (EPI) z = x - hv[S * t];
-            dst[S * t] = z;
+            const double z = EPI ? x - hv[off] : x;
+            dst[off] = z;
             if (ARG && am) {
                 const int e = A[t * kKeyStride + c];
-                am[S * t] = (int16_t)e;
+                am[off] = (int16_t)e;
                 amax = max(amax, abs(e));
             }
-            if (a.stats_out) {
-                const double y = W[(t + 1) * kKeyStride + c];
-                sp = fmax(sp, y - x);
-                sn = fmax(sn, x - y);
-                sa = fmax(sa, fabs(x));
-                if (EPI) {
-                    sa = fmax(sa, fabs(z));
-                    hi = fmax(hi, z);
-                    nlo = fmax(nlo, -z);
-                }
-            }
+            if (a.stats_out) fold_stats<EPI>(st, x, W[(t + 1) * kKeyStride + c], z);
+            off += S * (kBlock / C);
         }
     }
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
@@ -452,18 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
         amax = (int)wave_max((double)amax);
         if (threadIdx.x % kWave == 0) atomicMax(&a.flags[4 + a.axis], (uint32_t)amax);
     }
-    if (a.stats_out) {
-        block_max5(sp, sn, sa, hi, nlo, red);
-        if (threadIdx.x == 0) {
-            stat_put(a.stats_out, a.axis, sp);
-            stat_put(a.stats_out, 3 + a.axis, sn);
-            stat_put(a.stats_out, 6, sa);
-            if (EPI) {
-                stat_put(a.stats_out, 7, hi);
-                stat_put(a.stats_out, 8, nlo);
-            }
-        }
-    }
+    publish_stats<EPI>(st, a, red);
 }
 
 ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg)
