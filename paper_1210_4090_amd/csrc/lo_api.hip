@@ -52,6 +52,7 @@ struct lo_plan_s {
     uint64_t* stats = nullptr;   // kSlots * kSlotStride
     int* win = nullptr;          // windows of the current and next step: [2][2 * kMaxDim]
     WinParams winp;
+    WinParams* dwinp = nullptr;  // device copy read by the sweeps that compute the next windows
     uint32_t* flags = nullptr;   // kFlagWords
     uint32_t hflags[8] = {0};    // folded: [0] errors, [1+a] window used, [4+a] max |argmin|
     bool have_diag = false;
@@ -156,6 +157,7 @@ void free_plan(lo_plan_t p)
     if (p->bw_arg) (void)hipFree(p->bw_arg);
     if (p->bw_part) (void)hipFree(p->bw_part);
     if (p->dpofs) (void)hipFree(p->dpofs);
+    if (p->dwinp) (void)hipFree(p->dwinp);
     delete p;
 }
 
@@ -392,6 +394,18 @@ void fill_winparams(lo_plan_t p)
     W.b_stats = (int64_t)kSlots * kSlotStride;
     W.b_win = 4 * kMaxDim;
     W.pofs_b = p->nb > 1 ? p->dpofs : nullptr;
+    W.lag = 1;
+    W.hv_osc = 2.0 * p->hvmax;   // tau * (max V - min V) <= 2 max |tau V|
+}
+
+lo_status upload_winparams(lo_plan_t p)
+{
+    if (!p->dwinp) {
+        lo_status st = alloc((void**)&p->dwinp, sizeof(WinParams));
+        if (st) return st;
+    }
+    HIPCHK(hipMemcpy(p->dwinp, &p->winp, sizeof(WinParams), hipMemcpyHostToDevice));
+    return LO_OK;
 }
 
 // The device's one-sided window search, on the host table (for sizing halos).
@@ -532,12 +546,16 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.cq = p->dx[a] * p->dx[a] / (2.0 * p->d.tau);
         A.inv2c = 1.0 / (2.0 * A.cq);
         A.pofs = p->d.P[a] * p->d.tau / p->dx[a];
+        if (a == 0) {
+            // windows of step n + 1 from the statistics of u^n (slot n), one step early
+            A.winp_dev = p->dwinp;
+            A.win_slot = slot(p, n);
+            A.win_next = p->win + (size_t)((((n + 1) % 2) + 2) % 2) * 2 * kMaxDim;
+        }
         if (ev) HIPCHK(hipEventRecord(ev[2 * a], s));
         HIPCHK(launch_sweep(p->d.method, in[a], out[a], A, s));
         if (ev) HIPCHK(hipEventRecord(ev[2 * a + 1], s));
     }
-    HIPCHK(launch_windows(p->winp, slot(p, n + 1), p->win + (size_t)((((n + 1) % 2) + 2) % 2) * 2 * kMaxDim,
-                          p->flags, p->nb, s));
     if (out[p->ndim - 1] != u)
         HIPCHK(hipMemcpyAsync(u, out[p->ndim - 1], sizeof(double) * p->npts * p->nb, hipMemcpyDeviceToDevice, s));
     return LO_OK;
@@ -674,6 +692,11 @@ lo_status plan_create(const lo_desc* desc, const lo_potential* V, int nb, const 
     }
     choose_kernels(p);
     fill_winparams(p);
+    st = upload_winparams(p);
+    if (st) {
+        free_plan(p);
+        return st;
+    }
     *out = p;
     return LO_OK;
 }
@@ -719,6 +742,8 @@ lo_status lo_set_coef(lo_plan_t p, const double* coef)
     if (st) return st;
     HIPCHK(hipDeviceSynchronize());
     fill_winparams(p);
+    st = upload_winparams(p);
+    if (st) return st;
     // captured steps hold the old margins by value
     for (auto& g : p->graphs) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);

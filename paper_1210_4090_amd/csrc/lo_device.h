@@ -198,6 +198,10 @@ __device__ __forceinline__ int64_t batch_shift(SweepArgs& a, int64_t* koff)
     return uniform64(b * a.b_u);
 }
 
+// Block 0 (of each instance) of the sweep that carries them computes the
+// next step's windows; the sweeps of this step keep reading their own slot.
+__device__ __forceinline__ void maybe_next_windows(const SweepArgs& a);
+
 __device__ __forceinline__ int64_t remap_block(int64_t b, int64_t G)
 {
     // consecutive tiles of the same lines go to one XCD (blocks are dealt to
@@ -273,8 +277,8 @@ __device__ inline void next_windows(const WinParams& P, int64_t inst, const uint
     __shared__ int part[kMaxDim][4];
     __shared__ int caps[kMaxDim][4];
     const int w = threadIdx.x / kWave;
-    const double M = stat_get(slot, 6);
-    const double osc0 = stat_get(slot, 7) + stat_get(slot, 8);
+    const double M = stat_get(slot, 6) + (P.lag ? P.slack_extra : 0.0);
+    const double osc0 = stat_get(slot, 7) + stat_get(slot, 8) + (P.lag ? P.hv_osc : 0.0);
     if (w < 4) {
         for (int ax = 0; ax < P.ndim; ax++) {
             if (P.wfix[ax] > 0) continue;
@@ -284,7 +288,8 @@ __device__ inline void next_windows(const WinParams& P, int64_t inst, const uint
             if (level)
                 D = osc0 + P.osc_extra[ax];
             else
-                D = dir > 0 ? stat_get(slot, ax) + P.dvf[ax] : stat_get(slot, 3 + ax) + P.dvb[ax];
+                D = dir > 0 ? stat_get(slot, ax) + P.dvf[ax] * (P.lag ? 2.0 : 1.0)
+                            : stat_get(slot, 3 + ax) + P.dvb[ax] * (P.lag ? 2.0 : 1.0);
             const double sbase = 1.0 + M + P.slack_extra;
             int64_t est = 0;
             if (P.quad[ax]) {
@@ -324,6 +329,14 @@ __device__ inline void next_windows(const WinParams& P, int64_t inst, const uint
         }
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ void maybe_next_windows(const SweepArgs& a)
+{
+    if (a.win_next && blockIdx.x == 0) {
+        const int64_t b = blockIdx.y;
+        next_windows(*a.winp_dev, b, a.win_slot + b * a.b_stats, a.win_next + b * a.b_win, a.flags);
+    }
 }
 
 }  // namespace dev

@@ -307,6 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_row(const double* __restrict__
         if (threadIdx.x % kWave == 0) atomicMax(&a.flags[4 + a.axis], (uint32_t)amax);
     }
     publish_stats<EPI>(st, a, red);
+    maybe_next_windows(a);   // after this block's own work: off the critical path
 }
 
 // ---------------------------------------------------------------------------
@@ -444,6 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
         if (threadIdx.x % kWave == 0) atomicMax(&a.flags[4 + a.axis], (uint32_t)amax);
     }
     publish_stats<EPI>(st, a, red);
+    maybe_next_windows(a);   // after this block's own work: off the critical path
 }
 
 ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg)

@@ -64,6 +64,11 @@ struct WinParams {
     int64_t b_stats;
     int b_win;
     const double* pofs_b;          // [nb][kMaxDim] per-instance P tau / dx, nullptr: pofs[]
+    // lag = 1: the statistics are those of u^n and the windows are for step
+    // n + 1, one potential step later: forward differences grow by at most
+    // dvf / dvb, the oscillation by at most hv_osc, |w| by slack_extra
+    int lag;
+    double hv_osc;
 };
 
 // Everything a sweep kernel needs besides the arrays.
@@ -102,6 +107,11 @@ struct SweepArgs {
     int64_t b_stats;
     int b_win;
     const double* pofs_b;       // [nb][kMaxDim] per-instance P tau / dx (nullptr: pofs)
+    // the next step's windows, computed by block 0 (of each instance) from
+    // the statistics of this step's input (nullptr: not by this sweep)
+    const WinParams* winp_dev;
+    const uint64_t* win_slot;
+    int* win_next;
 };
 
 constexpr int kKindRow = 0;     // whole lines in LDS, unit stride

@@ -241,6 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__
             }
         }
     }
+    maybe_next_windows(a);   // after this block's own work: off the critical path
 }
 
 // ---------------------------------------------------------------------------
@@ -403,6 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
             }
         }
     }
+    maybe_next_windows(a);   // after this block's own work: off the critical path
 }
 
 // ---------------------------------------------------------------------------
