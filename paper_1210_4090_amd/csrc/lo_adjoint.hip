@@ -9,10 +9,10 @@
 // Scatter as a gather.  With a convex cost and the lowest-offset tie rule the
 // lifted argmin source of target i is nondecreasing in i (the Monge property
 // of k(i - j)), so the targets that choose a given source form one
-// contiguous run.  A block stages the int16 offsets of the targets that can
-// reach its tile of sources (a halo of max |offset| on each side), marks the
-// first and last target of every source's run, and each source sums its run
-// in increasing target order.  No atomics, so the result is deterministic and
+// contiguous run.  A block stages the int16 offsets and the upstream
+// gradients of the targets that can reach its tile of sources (a halo of max
+// |offset| on each side) in LDS, marks the first and last target of every
+// source's run, and each source sums its run in increasing target order.  No atomics, so the result is deterministic and
 // the additions happen in the order of a sequential loop over the grid.  A
 // line whose staged offsets are not monotone (possible only through rounding
 // near exact ties) is summed by scanning every target within the halo.
@@ -29,30 +29,31 @@ constexpr int kMaxLinesPerTile = 16;
 
 __device__ __forceinline__ int floor_div(int x, int n) { return x >= 0 ? x / n : -((n - 1 - x) / n); }
 
-__device__ __forceinline__ int64_t line_base(int64_t ln, int S, int N)
+__device__ __forceinline__ int64_t line_base(int ln, int S, int N)
 {
     return (ln % S) + (int64_t)S * N * (ln / S);
 }
 
 // One tile: C lines x R sources [r0, r0 + R) of the axis, targets
 // [r0 - h, r0 + R + h) staged (span = R + 2h positions, position p is the
-// lifted target r0 - h + p).
+// lifted target r0 - h + p) with their offsets and upstream gradients.
 __global__ __launch_bounds__(kBlock) void k_scatter(const int16_t* __restrict__ E, const double* __restrict__ lam,
                                                     double* __restrict__ out, double* __restrict__ Lam,
                                                     ScatterArgs a, uint32_t* flags)
 {
-    extern __shared__ int smi[];
+    extern __shared__ double smd[];
     __shared__ int nonmono[kMaxLinesPerTile];
     const int N = (int)a.g.n, S = (int)a.g.stride, C = a.C, R = a.R, h = a.h, span = a.span;
     const int nTB = (N + R - 1) / R;
-    const int64_t G = (int64_t)nTB * ((a.g.nlines + C - 1) / C);
-    const int64_t b = remap_block(blockIdx.x, G);
-    const int64_t lb = b / nTB;
-    const int r0 = (int)(b % nTB) * R;
+    const int G = nTB * (int)((a.g.nlines + C - 1) / C);    // indices fit 32 bits (grids < 2^31 points)
+    const int b = (int)remap_block(blockIdx.x, G);
+    const int lb = b / nTB;
+    const int r0 = (b - lb * nTB) * R;
     const int Rt = min(R, N - r0);
-    int* first = smi;                              // [C][R] first position of each source's run, -1: none
-    int* last = smi + C * R;                       // [C][R]
-    int16_t* es = (int16_t*)(smi + 2 * C * R);     // [C][span] offsets of the staged targets
+    double* ls = smd;                                // [C][span] upstream gradient of the staged targets
+    int* first = (int*)(ls + (size_t)C * span);      // [C][R] first position of each source's run, -1: none
+    int* last = first + C * R;                       // [C][R]
+    int16_t* es = (int16_t*)(last + C * R);          // [C][span] offsets of the staged targets
     const bool unit = S == 1;
     // a thread's line (strided axes: fixed, lines are adjacent in memory) and its step along positions
     const int cq = unit ? 0 : (int)threadIdx.x % C;
@@ -64,27 +65,48 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int16_t* __restrict__ 
     for (int c = c_lo; c < c_hi; c++)
         for (int j = q0; j < R; j += Q) first[c * R + j] = -1;
 
-    // stage offsets (targets of lines beyond the grid read as offset 0, which
-    // lands outside every tile's source range only for themselves)
+    // stage offsets and gradients (lines beyond the grid read as offset 0 and
+    // gradient 0; they are never written)
     const int T0 = r0 - h;                     // lifted target of position 0
     const int t0r = T0 - floor_div(T0, N) * N; // its residue
     const int qstep = Q % N;
     bool bad = false;
     for (int c = c_lo; c < c_hi; c++) {
-        const int64_t ln = lb * C + c;
+        const int ln = lb * C + c;
         if (ln >= a.g.nlines) {
-            for (int p = q0; p < span; p += Q) es[c * span + p] = 0;
+            for (int p = q0; p < span; p += Q) {
+                es[c * span + p] = 0;
+                ls[c * span + p] = 0.0;
+            }
             continue;
         }
         const int64_t base = line_base(ln, S, N);
         int t = t0r + q0 % N;
         if (t >= N) t -= N;
-        for (int p = q0; p < span; p += Q) {
-            const int e = E[base + (int64_t)t * S];
-            bad |= e > h || e < -h;
-            es[c * span + p] = (int16_t)e;
-            t += qstep;
-            if (t >= N) t -= N;
+        // kU positions per round with all their loads in flight at once
+        constexpr int kU = 8;
+        for (int p0 = q0; p0 < span; p0 += kU * Q) {
+            int ev[kU];
+            double lv[kU];
+#pragma unroll
+            for (int u = 0; u < kU; u++) {
+                if (p0 + u * Q < span) {
+                    const int64_t x = base + (int64_t)t * S;
+                    ev[u] = E[x];
+                    lv[u] = lam[x];
+                }
+                t += qstep;
+                if (t >= N) t -= N;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; u++) {
+                const int p = p0 + u * Q;
+                if (p < span) {
+                    bad |= ev[u] > h || ev[u] < -h;
+                    es[c * span + p] = (int16_t)ev[u];
+                    ls[c * span + p] = lv[u];
+                }
+            }
         }
     }
     if (bad) atomicOr(&flags[0], kErrAdjointHalo);
@@ -108,10 +130,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int16_t* __restrict__ 
     __syncthreads();
 
     for (int c = c_lo; c < c_hi; c++) {
-        const int64_t ln = lb * C + c;
+        const int ln = lb * C + c;
         if (ln >= a.g.nlines) continue;
         const int64_t base = line_base(ln, S, N);
         const int16_t* el = es + c * span;
+        const double* ll = ls + c * span;
         const bool mono = nonmono[c] == 0;
         for (int j = q0; j < Rt; j += Q) {
             double acc = 0.0;
@@ -124,28 +147,17 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int16_t* __restrict__ 
                     const int Tf = T0 + f;
                     const int kN = (floor_div(Tf, N) + 1) * N;
                     const int split = (kN <= T0 + l) ? kN - T0 : f;   // first position of the upper part
-                    int t = kN <= T0 + l ? 0 : Tf - (kN - N);
-                    for (int p = split; p <= l; p++) {
-                        acc = acc + lam[base + (int64_t)t * S];
-                        t++;
-                    }
-                    t = Tf - (kN - N);
-                    for (int p = f; p < split; p++) {
-                        acc = acc + lam[base + (int64_t)t * S];
-                        t++;
-                    }
+                    for (int p = split; p <= l; p++) acc = acc + ll[p];
+                    for (int p = f; p < split; p++) acc = acc + ll[p];
                 }
             } else {
                 const int pe = min(j + 2 * h, span - 1);
-                int t = T0 + j - floor_div(T0 + j, N) * N;
-                for (int p = j; p <= pe; p++) {
-                    if (p - h + el[p] == j) acc = acc + lam[base + (int64_t)t * S];
-                    if (++t == N) t = 0;
-                }
+                for (int p = j; p <= pe; p++)
+                    if (p - h + el[p] == j) acc = acc + ll[p];
             }
             const int64_t x = base + (int64_t)(r0 + j) * S;
             out[x] = acc;
-            if (Lam) Lam[x] = Lam[x] + lam[x];
+            if (Lam) Lam[x] = Lam[x] + ll[h + j];
         }
     }
 }
@@ -197,7 +209,8 @@ __global__ __launch_bounds__(kBlock) void k_project_sum(const double* __restrict
 
 size_t scatter_lds_bytes(int C, int R, int h)
 {
-    return sizeof(int) * 2 * (size_t)C * R + sizeof(int16_t) * (size_t)C * (R + 2 * (size_t)h);
+    const size_t span = R + 2 * (size_t)h;
+    return sizeof(double) * (size_t)C * span + sizeof(int) * 2 * (size_t)C * R + sizeof(int16_t) * (size_t)C * span;
 }
 
 bool scatter_layout(const AxisGeom& g, int h, size_t lds_max, ScatterArgs* a)
@@ -213,9 +226,10 @@ bool scatter_layout(const AxisGeom& g, int h, size_t lds_max, ScatterArgs* a)
         R = (int)std::min<int64_t>(N, 128);
         C = kMaxLinesPerTile;
     }
-    const size_t budget = std::min<size_t>(lds_max, 64 * 1024);
+    // strided axes keep 16 lines (128-byte rows) and shorten the tile first
+    const size_t budget = std::min<size_t>(lds_max, 40 * 1024);
+    while (scatter_lds_bytes(C, R, h) > budget && R > 32) R /= 2;
     while (scatter_lds_bytes(C, R, h) > budget && C > 1) C /= 2;
-    while (scatter_lds_bytes(C, R, h) > budget && R > 64) R /= 2;
     if (scatter_lds_bytes(C, R, h) > lds_max) return false;
     a->C = C;
     a->R = R;
