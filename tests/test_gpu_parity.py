@@ -285,3 +285,35 @@ def test_config3_full_size_first_steps(torch_dev, orc, method):
     u = _gpu(torch, w.u0)
     p.run(u, 2)
     _check(u.cpu().numpy(), ref, method)
+
+
+@pytest.mark.parametrize("n,tau,P", [((64,), 0.05, (0.3,)), ((256,), 0.02, (-0.4,)), ((48, 40), 0.04, (0.2, -0.1)),
+                                     ((72, 33), 0.03, (0.1, 0.5))])
+def test_fast_argmins_attain_the_value(torch_dev, orc, n, tau, P):
+    """Fast-path argmins (in-place row sweeps included): every offset
+    reproduces the returned value exactly from the plan's cost table, and
+    equals the oracle's offset wherever the two values agree."""
+    torch = torch_dev
+    print_case("fast argmins", n)
+    u0 = wl.smooth_grid(list(n), 500) + 0.05 * wl.random_grid(list(n), 501)
+    V = wl.smooth_grid(list(n), 502)
+    p = _plan(torch, n, tau, P, V, "fast")
+    u = _gpu(torch, u0)
+    arg = p.step(u, 0, argmin=True).cpu().numpy().astype(np.int64)
+    got = u.cpu().numpy()
+    ref, rarg = orc.step(u0, tau, P, V=V, with_argmin=True)
+    hv = tau * V
+    # replay the sweeps with the reported offsets (axis 0 first, numpy order reversed)
+    w = u0.copy()
+    for a in range(len(n)):
+        ax = len(n) - 1 - a
+        N = n[a]
+        e = arg[a]
+        k = p.kinetic_table(a, -2 * N, 4 * N + 1)
+        idx = np.arange(N).reshape([-1 if d == ax else 1 for d in range(len(n))])
+        src = np.take_along_axis(w, (idx + e) % N, axis=ax)
+        w = src + k[2 * N - e]
+    assert np.array_equal(w - hv, got)
+    same = got == ref
+    assert same.mean() > 0.99
+    assert np.array_equal(arg[:, same], rarg[:, same].astype(np.int64))
