@@ -47,17 +47,26 @@
 
 #include <algorithm>
 
+#ifndef LO_ROW_CH
+#define LO_ROW_CH 8
+#endif
+
 namespace lo {
 
 namespace {
 
 using namespace dev;
-constexpr int kCh = 8;           // sources per chunk
+constexpr int kCh = 8;           // sources per chunk (tile kernel)
+constexpr int kRowCh = LO_ROW_CH;        // points per thread (row kernel)
+constexpr int kRowBlock = 2048 / kRowCh; // threads per row-kernel block: 2048-point tiles
 constexpr int kTileLines = 16;   // TILE: lines side by side
 constexpr int kKeyStride = kTileLines + 1;   // TILE key row stride (doubles)
 constexpr double kEps = 1e-6;    // claim widening, in cells
 
-__device__ __forceinline__ int sk(int x) { return x + (x >> 3); }
+// skewed LDS slot of key x for chunks of CH points: one pad slot per chunk,
+// so lanes that walk chunk-strided keys hit distinct banks
+template <int CH>
+__device__ __forceinline__ int skc(int x) { return x + x / CH; }
 
 }  // namespace
 
@@ -92,23 +101,23 @@ namespace {
 // lifted target t.  PASS 0: atomic minimum of the candidate into W;
 // PASS 1: among the candidates equal to W, atomic minimum of the offset
 // (source - target) into A.
-template <int PASS, typename KeyOf>
-__device__ __forceinline__ void claim_chunk(const double (&uu)[kCh + 2], int p0, int plast, int tmin, int tmax,
+template <int PASS, int CH, typename KeyOf>
+__device__ __forceinline__ void claim_chunk(const double (&uu)[CH + 2], int p0, int plast, int tmin, int tmax,
                                             const double* KT, int KH, double inv2c, double pofs, double* W,
                                             int* A, KeyOf key)
 {
     // crossing k lies between sources p0 - 1 + k and p0 + k
-    int lo[kCh + 1], hi[kCh + 1];
+    int lo[CH + 1], hi[CH + 1];
     double jh = (double)p0 - 0.5;
 #pragma unroll
-    for (int k = 0; k <= kCh; k++) {
+    for (int k = 0; k <= CH; k++) {
         const double sg = jh + ((uu[k + 1] - uu[k]) * inv2c + pofs);
         lo[k] = (int)floor(sg - kEps);   // source p0 + k claims from lo[k] + 1
         hi[k] = (int)floor(sg + kEps);   // source p0 - 1 + k claims up to hi[k]
         jh += 1.0;
     }
 #pragma unroll
-    for (int k = 0; k < kCh; k++) {
+    for (int k = 0; k < CH; k++) {
         const int p = p0 + k;
         if (p > plast) break;
         const int tlo = max(max(lo[k], p - KH - 1), tmin - 1) + 1;
@@ -167,8 +176,8 @@ __device__ __forceinline__ void publish_stats(SweepStats& st, const SweepArgs& a
 // writes them as targets.  Keys live in LDS in the skewed layout; claims wrap
 // around the row.  Persistent: a block walks tiles blockIdx.x, + gridDim.x, ...
 // ---------------------------------------------------------------------------
-template <int EPI, int ARG>
-__global__ __launch_bounds__(kBlock) void k_claim_row(const double* __restrict__ in, double* __restrict__ out,
+template <int EPI, int ARG, int CH, int BS>
+__global__ __launch_bounds__(BS) void k_claim_row(const double* __restrict__ in, double* __restrict__ out,
                                                       const double* __restrict__ kc, SweepArgs a, ClaimLds L,
                                                       double inv2c, double pofs)
 {
@@ -184,9 +193,9 @@ __global__ __launch_bounds__(kBlock) void k_claim_row(const double* __restrict__
     }
     const int N = (int)a.g.n;
     const int KH = L.KH, nr = L.nr;
-    const int cpr = N >> 3;                       // chunks per row
+    const int cpr = N / CH;                       // chunks per row
     const int r = (int)threadIdx.x / cpr;         // row of this thread within a tile
-    const int p0 = ((int)threadIdx.x - r * cpr) << 3;
+    const int p0 = ((int)threadIdx.x - r * cpr) * CH;
     const bool act = r < nr;
     const int g0 = r * N + p0;                    // first key of this thread (unskewed)
     double* KT = sm;
@@ -198,14 +207,14 @@ __global__ __launch_bounds__(kBlock) void k_claim_row(const double* __restrict__
     int wm = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis + 1];
     wp = __builtin_amdgcn_readfirstlane(wp);
     wm = __builtin_amdgcn_readfirstlane(wm);
-    for (int i = threadIdx.x; i < 2 * KH + 1; i += kBlock) {
+    for (int i = threadIdx.x; i < 2 * KH + 1; i += BS) {
         const int s = i - KH;
         KT[i] = (s >= -a.kin.kcap && s <= a.kin.kcap) ? kc[s] : INFINITY;
     }
     // claims reach |t - p| <= W + 1 for the minimisers; one wrap needs KH < N
     const bool fast = wp + 1 <= KH && wm + 1 <= KH && KH < N;
     const int kbase = r * N;
-    auto key = [N, kbase](int t) { return sk(kbase + (t < 0 ? t + N : (t >= N ? t - N : t))); };
+    auto key = [N, kbase](int t) { return skc<CH>(kbase + (t < 0 ? t + N : (t >= N ? t - N : t))); };
 
     SweepStats st;
     int amax = 0;
@@ -215,35 +224,35 @@ __global__ __launch_bounds__(kBlock) void k_claim_row(const double* __restrict__
         const int64_t row = tile * nr + r;
         const bool ok = act && row < a.g.nlines;
         const double* __restrict__ src = in + row * N;
-        double uu[kCh + 2];
+        double uu[CH + 2];
         if (ok) {
             uu[0] = src[p0 == 0 ? N - 1 : p0 - 1];
             const double2* s2 = (const double2*)(src + p0);
 #pragma unroll
-            for (int k = 0; k < kCh / 2; k++) {
+            for (int k = 0; k < CH / 2; k++) {
                 const double2 v = s2[k];
                 uu[1 + 2 * k] = v.x;
                 uu[2 + 2 * k] = v.y;
             }
-            uu[kCh + 1] = src[p0 + kCh == N ? 0 : p0 + kCh];
+            uu[CH + 1] = src[p0 + CH == N ? 0 : p0 + CH];
 #pragma unroll
-            for (int k = 0; k < kCh; k++) {
-                W[sk(g0 + k)] = INFINITY;
-                if (ARG) A[sk(g0 + k)] = 0x7fffffff;
+            for (int k = 0; k < CH; k++) {
+                W[skc<CH>(g0 + k)] = INFINITY;
+                if (ARG) A[skc<CH>(g0 + k)] = 0x7fffffff;
             }
         }
         __syncthreads();
         if (fast) {
-            if (ok) claim_chunk<0>(uu, p0, N - 1, -KH, N - 1 + KH, KT, KH, inv2c, pofs, W, A, key);
+            if (ok) claim_chunk<0, CH>(uu, p0, N - 1, -KH, N - 1 + KH, KT, KH, inv2c, pofs, W, A, key);
             __syncthreads();
             if (ARG) {
-                if (ok) claim_chunk<1>(uu, p0, N - 1, -KH, N - 1 + KH, KT, KH, inv2c, pofs, W, A, key);
+                if (ok) claim_chunk<1, CH>(uu, p0, N - 1, -KH, N - 1 + KH, KT, KH, inv2c, pofs, W, A, key);
                 __syncthreads();
             }
         } else {
             // exhaustive window over the wrapped row, sources from global memory
             if (ok) {
-                for (int k = 0; k < kCh; k++) {
+                for (int k = 0; k < CH; k++) {
                     const int t = p0 + k;
                     double best = INFINITY;
                     int arg = 0;
@@ -257,43 +266,43 @@ __global__ __launch_bounds__(kBlock) void k_claim_row(const double* __restrict__
                         }
                         if (++j == N) j = 0;
                     }
-                    W[sk(g0 + k)] = best;
-                    if (ARG) A[sk(g0 + k)] = arg;
+                    W[skc<CH>(g0 + k)] = best;
+                    if (ARG) A[skc<CH>(g0 + k)] = arg;
                 }
             }
             __syncthreads();
         }
         if (ok) {
-            double x[kCh + 1];
+            double x[CH + 1];
 #pragma unroll
-            for (int k = 0; k < kCh; k++) x[k] = W[sk(g0 + k)];
-            x[kCh] = W[sk(kbase + (p0 + kCh == N ? 0 : p0 + kCh))];
-            double z[kCh];
+            for (int k = 0; k < CH; k++) x[k] = W[skc<CH>(g0 + k)];
+            x[CH] = W[skc<CH>(kbase + (p0 + CH == N ? 0 : p0 + CH))];
+            double z[CH];
             if (EPI) {
                 const double2* h2 = (const double2*)(a.hv + row * N + p0);
 #pragma unroll
-                for (int k = 0; k < kCh / 2; k++) {
+                for (int k = 0; k < CH / 2; k++) {
                     const double2 v = h2[k];
                     z[2 * k] = x[2 * k] - v.x;
                     z[2 * k + 1] = x[2 * k + 1] - v.y;
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < kCh; k++) z[k] = x[k];
+                for (int k = 0; k < CH; k++) z[k] = x[k];
             }
             double2* d2 = (double2*)(out + row * N + p0);
 #pragma unroll
-            for (int k = 0; k < kCh / 2; k++) d2[k] = make_double2(z[2 * k], z[2 * k + 1]);
+            for (int k = 0; k < CH / 2; k++) d2[k] = make_double2(z[2 * k], z[2 * k + 1]);
 #pragma unroll
-            for (int k = 0; k < kCh; k++) {
+            for (int k = 0; k < CH; k++) {
                 bad |= !(x[k] < INFINITY);
                 if (a.stats_out) fold_stats<EPI>(st, x[k], x[k + 1], z[k]);
             }
             if (ARG && a.argmin) {
                 int16_t* am = a.argmin + row * N + p0;
 #pragma unroll
-                for (int k = 0; k < kCh; k++) {
-                    const int e = A[sk(g0 + k)];
+                for (int k = 0; k < CH; k++) {
+                    const int e = A[skc<CH>(g0 + k)];
                     am[k] = (int16_t)e;
                     amax = max(amax, abs(e));
                 }
@@ -389,9 +398,9 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
                 }
                 auto key = [r0](int t) { return (t - r0) * kKeyStride; };
                 if (pass == 0)
-                    claim_chunk<0>(uu, p0, pB, r0, r0 + NT - 1, KT, KH, inv2c, pofs, W + c, A + c, key);
+                    claim_chunk<0, kCh>(uu, p0, pB, r0, r0 + NT - 1, KT, KH, inv2c, pofs, W + c, A + c, key);
                 else
-                    claim_chunk<1>(uu, p0, pB, r0, r0 + NT - 1, KT, KH, inv2c, pofs, W + c, A + c, key);
+                    claim_chunk<1, kCh>(uu, p0, pB, r0, r0 + NT - 1, KT, KH, inv2c, pofs, W + c, A + c, key);
             }
             __syncthreads();
         }
@@ -457,7 +466,7 @@ ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg)
         L.row = 1;
         L.nr = (int)std::max<int64_t>(1, 2048 / N);   // whole rows, at most 2048 points per tile
         const int g = L.nr * (int)N;
-        L.RS = g + (g >> 3) + 1;                     // skewed keys
+        L.RS = g + g / kRowCh + 1;                   // skewed keys
         L.NT = 0;
     } else {
         L.row = 0;
@@ -478,13 +487,16 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
 #define LO_CLAIM_LAUNCH(K, E, A)                                                                             \
     hipLaunchKernelGGL((K<E, A>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out, a.kin.k, a, L, \
                        inv2c, pofs)
+#define LO_ROW_LAUNCH(E, A)                                                                                  \
+    hipLaunchKernelGGL((k_claim_row<E, A, kRowCh, kRowBlock>), dim3((unsigned)grid, a.nb), dim3(kRowBlock), \
+                       lds, s, in, out, a.kin.k, a, L, inv2c, pofs)
     if (ROW) {
         if (epi) {
-            if (arg) LO_CLAIM_LAUNCH(k_claim_row, 1, 1);
-            else LO_CLAIM_LAUNCH(k_claim_row, 1, 0);
+            if (arg) LO_ROW_LAUNCH(1, 1);
+            else LO_ROW_LAUNCH(1, 0);
         } else {
-            if (arg) LO_CLAIM_LAUNCH(k_claim_row, 0, 1);
-            else LO_CLAIM_LAUNCH(k_claim_row, 0, 0);
+            if (arg) LO_ROW_LAUNCH(0, 1);
+            else LO_ROW_LAUNCH(0, 0);
         }
     } else {
         if (epi) {
@@ -496,6 +508,7 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
         }
     }
 #undef LO_CLAIM_LAUNCH
+#undef LO_ROW_LAUNCH
     return hipGetLastError();
 }
 
