@@ -79,12 +79,12 @@ def timed_runs(torch, plan, u0, steps, K, W):
     return time.perf_counter() - t0, u
 
 
-def measure_workload(torch, w, method, K, W, steps=None):
+def measure_workload(torch, w, method, K, W, steps=None, autotune=False):
     from paper_1210_4090_amd.lo import Plan
     steps = w.steps if steps is None else steps
     V = torch.as_tensor(w.V, device="cuda")
     u0 = torch.as_tensor(w.u0, device="cuda")
-    plan = Plan(w.n, w.tau, w.P, V=V, method=method)
+    plan = Plan(w.n, w.tau, w.P, V=V, method=method, autotune=autotune)
     dt, u = timed_runs(torch, plan, u0, steps, K, W)
     rate = w.npts * steps * K / dt
     # per-kernel durations over one full run from u0, HIP events on the stream
@@ -100,7 +100,7 @@ def measure_workload(torch, w, method, K, W, steps=None):
             "window_max": wins, "plan": plan, "V": V, "u0": u0}
 
 
-def measure_adjoint(torch, method, every=50, reps=2):
+def measure_adjoint(torch, method, every=50, reps=2, autotune=False):
     """Differentiation workload (1024^2, 500 steps, 64 Fourier modes of V):
     forward with FP64 checkpoints every `every` steps, then the reverse pass
     (segment recompute with int16 argmins, reverse sweeps, projection)."""
@@ -109,7 +109,7 @@ def measure_adjoint(torch, method, every=50, reps=2):
     from paper_1210_4090_amd.lo import Plan
     w, _ = wl.config5()
     B = torch.as_tensor(w.basis, device="cuda")
-    plan = Plan(w.n, w.tau, w.P, basis=B, coef=w.coef, method=method)
+    plan = Plan(w.n, w.tau, w.P, basis=B, coef=w.coef, method=method, autotune=autotune)
     u0 = torch.as_tensor(w.u0, device="cuda")
     gT = torch.as_tensor(np.random.default_rng(5).standard_normal(w.u0.shape), device="cuda")
     u = torch.empty_like(u0)
@@ -257,6 +257,17 @@ def main():
         extras["batched_hbar_512"] = measure_hbar(torch, args.method)
         log("batched hbar: %s" % extras["batched_hbar_512"])
         extras["fwd_adjoint_1024^2_500steps"] = measure_adjoint(torch, args.method)
+        if args.method == "fast":
+            mt = measure_workload(torch, w, "fast", 2, 1, autotune=True)
+            extras["headline_workload_autotuned"] = {"updates_per_s": mt["rate"], "ms_per_run": mt["ms_per_run"],
+                                                    "kernel_ms": mt["kernel_ms"]}
+            del mt
+            m3t = measure_workload(torch, w3, "fast", 2, 1, autotune=True)
+            extras["3d_torus_256^3_200steps_autotuned"] = {"updates_per_s": m3t["rate"],
+                                                          "all_axis_GBs": m3t["all_axis_GBs"]}
+            del m3t
+            extras["fwd_adjoint_1024^2_500steps_autotuned"] = measure_adjoint(torch, "fast", autotune=True)
+            log("autotuned: %s" % {k: v for k, v in extras.items() if "autotuned" in k})
         log("fwd+adjoint: %s" % extras["fwd_adjoint_1024^2_500steps"])
         out["extras"] = extras
     if not args.no_cpu:

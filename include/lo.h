@@ -64,6 +64,10 @@ typedef enum {
 
 /* flags */
 #define LO_FLAG_NO_GRAPH 1u   /* lo_run: launch kernels directly, no HIP graph */
+#define LO_FLAG_AUTOTUNE 2u   /* LO_FAST: the first lo_run times each fast sweep's launch shapes
+                                 (tile length, points per thread) on a copy of its input for a
+                                 few steps and keeps the fastest per axis; results do not depend
+                                 on the shape */
 
 typedef struct {
     int32_t ndim;              /* 1..3 */

@@ -20,6 +20,7 @@ LO_ERR_WINDOW = 5
 LO_BRUTE = 0
 LO_FAST = 1
 LO_FLAG_NO_GRAPH = 1
+LO_FLAG_AUTOTUNE = 2
 
 _f64p = ctypes.POINTER(ctypes.c_double)
 

@@ -33,6 +33,10 @@ struct lo_plan_s {
     int halo[kMaxDim] = {0, 0, 0};       // halo of the next launches (adapted by lo_run)
     int halo_max[kMaxDim] = {0, 0, 0};   // largest halo the LDS budget allows
     int tile_rows[kMaxDim] = {0, 0, 0};
+    int tile_fix[kMaxDim] = {0, 0, 0};    // fast tiles: length chosen by the tuner (0: from the halo)
+    int row_ch[kMaxDim] = {8, 8, 8};      // fast rows: points per thread
+    bool tuned = false;
+    double* tune_u = nullptr;             // the tuner's copy of the input
     bool fast[kMaxDim] = {false, false, false};
     // potential
     int nmodes = 0;
@@ -158,6 +162,7 @@ void free_plan(lo_plan_t p)
     if (p->bw_part) (void)hipFree(p->bw_part);
     if (p->dpofs) (void)hipFree(p->dpofs);
     if (p->dwinp) (void)hipFree(p->dwinp);
+    if (p->tune_u) (void)hipFree(p->tune_u);
     delete p;
 }
 
@@ -427,7 +432,7 @@ int choose_halo(lo_plan_t p, int a, int W)
     H = std::max(8, std::min(H, p->halo_max[a]));
     // fast tiles: longer tiles when the window's halo is wide (fewer halo
     // sources per target), shorter ones keep more blocks resident otherwise
-    if (p->fast[a] && p->kind[a] == kKindTile) p->tile_rows[a] = H >= 40 ? 256 : 128;
+    if (p->fast[a] && p->kind[a] == kKindTile) p->tile_rows[a] = p->tile_fix[a] > 0 ? p->tile_fix[a] : (H >= 40 ? 256 : 128);
     return H;
 }
 
@@ -530,6 +535,7 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.stats_clear = a == 0 ? slot(p, n + 2) : nullptr;
         A.win_in = p->win + (size_t)(((n % 2) + 2) % 2) * 2 * kMaxDim;
         A.grid_cap = p->grid_cap;
+        A.row_ch = p->row_ch[a];
         A.nb = p->nb;
         A.b_u = p->npts;
         A.b_k = 2 * p->kcap[a] + 1;
@@ -541,6 +547,11 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.argmin = argmin ? argmin + (size_t)a * p->npts : nullptr;
         A.halo = p->halo[a];
         A.tile_rows = p->tile_rows[a];
+        if (argmin && p->fast[a]) {
+            // argmin sweeps keep the default shapes (the tuner times the plain sweeps)
+            A.row_ch = 8;
+            if (p->kind[a] == kKindTile) A.tile_rows = p->halo[a] >= 40 ? 256 : 128;
+        }
         A.fast = p->fast[a] ? 1 : 0;
         A.quad = p->user_table[a] ? 0 : 1;
         A.cq = p->dx[a] * p->dx[a] / (2.0 * p->d.tau);
@@ -617,6 +628,68 @@ lo_status backward_buffers(lo_plan_t p, int64_t steps, bool coef)
         if (!st) p->bw_arg_steps = steps;
     }
     return st;
+}
+
+// Launch-shape tuner (LO_FLAG_AUTOTUNE): time kTuneSteps steps of every
+// candidate shape on a copy of u and keep, per axis, the shape whose sweep
+// was fastest.  Every shape computes the same values (the minimum over a
+// target's claimants does not depend on how sources are grouped), so the
+// choice only affects speed.
+constexpr int kTuneSteps = 8;
+
+lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
+{
+    p->tuned = true;
+    bool any = false;
+    for (int a = 0; a < p->ndim; a++) any |= p->fast[a];
+    if (!any) return LO_OK;
+    const size_t bytes = sizeof(double) * (size_t)p->npts * p->nb;
+    if (!p->tune_u) {
+        lo_status st = alloc((void**)&p->tune_u, bytes);
+        if (st) return st;
+    }
+    static const int kR[2] = {128, 256}, kC[2] = {8, 4};
+    double ms[2][2][kMaxDim] = {};
+    hipEvent_t ev[2 * kMaxDim];
+    for (int i = 0; i < 2 * p->ndim; i++) HIPCHK(hipEventCreate(&ev[i]));
+    lo_status st = LO_OK;
+    for (int ci = 0; ci < 2 && !st; ci++) {
+        for (int ri = 0; ri < 2 && !st; ri++) {
+            for (int a = 0; a < p->ndim; a++) {
+                if (p->kind[a] == kKindTile) p->tile_fix[a] = kR[ri];
+                else p->row_ch[a] = kC[ci];
+            }
+            if (hipMemcpyAsync(p->tune_u, u, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) st = LO_ERR_HIP;
+            if (!st) st = prologue(p, p->tune_u, n0, s);
+            for (int k = 0; k < kTuneSteps && !st; k++) {
+                st = enqueue_step(p, p->tune_u, n0 + k, nullptr, s, ev);
+                if (st) break;
+                if (hipEventSynchronize(ev[2 * p->ndim - 1]) != hipSuccess) st = LO_ERR_HIP;
+                for (int a = 0; a < p->ndim && !st && k > 0; a++) {   // step n0 warms up
+                    float t = 0.f;
+                    if (hipEventElapsedTime(&t, ev[2 * a], ev[2 * a + 1]) != hipSuccess) st = LO_ERR_HIP;
+                    ms[ci][ri][a] += t;
+                }
+            }
+        }
+    }
+    for (int i = 0; i < 2 * p->ndim; i++) (void)hipEventDestroy(ev[i]);
+    if (st) return st;
+    for (int a = 0; a < p->ndim; a++) {
+        if (p->kind[a] == kKindTile) {
+            const double t128 = ms[0][0][a] + ms[1][0][a], t256 = ms[0][1][a] + ms[1][1][a];
+            p->tile_fix[a] = t256 < t128 ? 256 : 128;
+        } else {
+            const double c8 = ms[0][0][a] + ms[0][1][a], c4 = ms[1][0][a] + ms[1][1][a];
+            p->row_ch[a] = c4 < c8 ? 4 : 8;
+        }
+    }
+    // the run proper starts from its own prologue; captured steps used other shapes
+    for (auto& g : p->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = lo_plan_s::GraphEntry();
+    }
+    return LO_OK;
 }
 
 // A plan for nb instances that share the grid, time step and potential and
@@ -806,7 +879,12 @@ lo_status lo_run(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckp
     if (!p || !u || nsteps < 0) return LO_ERR_INVALID;
     if (ckpt && ckpt_every <= 0) return LO_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    lo_status st = prologue(p, u, n0, s);
+    lo_status st = LO_OK;
+    if ((p->d.flags & LO_FLAG_AUTOTUNE) && !p->tuned) {
+        st = autotune(p, u, n0, s);
+        if (st) return st;
+    }
+    st = prologue(p, u, n0, s);
     if (st) return st;
     const bool use_graph = graphable(p) && !ckpt;
     int64_t done = 0;

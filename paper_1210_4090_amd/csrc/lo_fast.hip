@@ -47,9 +47,6 @@
 
 #include <algorithm>
 
-#ifndef LO_ROW_CH
-#define LO_ROW_CH 8
-#endif
 
 namespace lo {
 
@@ -57,8 +54,7 @@ namespace {
 
 using namespace dev;
 constexpr int kCh = 8;           // sources per chunk (tile kernel)
-constexpr int kRowCh = LO_ROW_CH;        // points per thread (row kernel)
-constexpr int kRowBlock = 2048 / kRowCh; // threads per row-kernel block: 2048-point tiles
+constexpr int kRowPoints = 2048; // row kernel: points per tile (points per thread x threads)
 constexpr int kTileLines = 16;   // TILE: lines side by side
 constexpr int kKeyStride = kTileLines + 1;   // TILE key row stride (doubles)
 constexpr double kEps = 1e-6;    // claim widening, in cells
@@ -457,7 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
     maybe_next_windows(a);   // after this block's own work: off the critical path
 }
 
-ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg)
+ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg, int row_ch)
 {
     ClaimLds L;
     L.arg = arg ? 1 : 0;
@@ -466,7 +462,7 @@ ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg)
         L.row = 1;
         L.nr = (int)std::max<int64_t>(1, 2048 / N);   // whole rows, at most 2048 points per tile
         const int g = L.nr * (int)N;
-        L.RS = g + g / kRowCh + 1;                   // skewed keys
+        L.RS = g + g / row_ch + 1;                   // skewed keys
         L.NT = 0;
     } else {
         L.row = 0;
@@ -487,9 +483,14 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
 #define LO_CLAIM_LAUNCH(K, E, A)                                                                             \
     hipLaunchKernelGGL((K<E, A>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out, a.kin.k, a, L, \
                        inv2c, pofs)
-#define LO_ROW_LAUNCH(E, A)                                                                                  \
-    hipLaunchKernelGGL((k_claim_row<E, A, kRowCh, kRowBlock>), dim3((unsigned)grid, a.nb), dim3(kRowBlock), \
-                       lds, s, in, out, a.kin.k, a, L, inv2c, pofs)
+#define LO_ROW_LAUNCH_CH(E, A, CH)                                                                            \
+    hipLaunchKernelGGL((k_claim_row<E, A, CH, kRowPoints / CH>), dim3((unsigned)grid, a.nb),                  \
+                       dim3(kRowPoints / CH), lds, s, in, out, a.kin.k, a, L, inv2c, pofs)
+#define LO_ROW_LAUNCH(E, A)                                                                                    \
+    do {                                                                                                       \
+        if (a.row_ch == 4) LO_ROW_LAUNCH_CH(E, A, 4);                                                          \
+        else LO_ROW_LAUNCH_CH(E, A, 8);                                                                        \
+    } while (0)
     if (ROW) {
         if (epi) {
             if (arg) LO_ROW_LAUNCH(1, 1);
@@ -509,6 +510,7 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
     }
 #undef LO_CLAIM_LAUNCH
 #undef LO_ROW_LAUNCH
+#undef LO_ROW_LAUNCH_CH
     return hipGetLastError();
 }
 
@@ -516,22 +518,25 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
 
 size_t fast_lds_for(int kind, int64_t N, int tile_rows, int H)
 {
-    return claim_lds_bytes(claim_layout(kind, N, tile_rows, H, true));
+    return claim_lds_bytes(claim_layout(kind, N, tile_rows, H, true, 4));   // the larger row layout
 }
 
 hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double cq, double inv2c, double pofs,
                        hipStream_t s)
 {
     (void)cq;
-    const ClaimLds L = claim_layout(a.kind, a.g.n, a.tile_rows, a.halo, a.argmin != nullptr);
+    const int row_ch = a.row_ch == 4 ? 4 : 8;
+    SweepArgs b = a;
+    b.row_ch = row_ch;
+    const ClaimLds L = claim_layout(a.kind, a.g.n, a.tile_rows, a.halo, a.argmin != nullptr, row_ch);
     // ROW: persistent blocks, at most grid_cap along x, each walks several tiles
     const int64_t cap = std::max(1, a.grid_cap);
     if (a.kind == kKindRow) {
         const int64_t tiles = (a.g.nlines + L.nr - 1) / L.nr;
-        return launch_claim_t<1>(in, out, a, L, inv2c, pofs, std::min(tiles, cap), s);
+        return launch_claim_t<1>(in, out, b, L, inv2c, pofs, std::min(tiles, cap), s);
     }
     const int64_t tiles = ((a.g.n + a.tile_rows - 1) / a.tile_rows) * ((a.g.nlines + kTileLines - 1) / kTileLines);
-    return launch_claim_t<0>(in, out, a, L, inv2c, pofs, tiles, s);
+    return launch_claim_t<0>(in, out, b, L, inv2c, pofs, tiles, s);
 }
 
 }  // namespace lo

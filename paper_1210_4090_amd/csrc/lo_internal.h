@@ -101,6 +101,7 @@ struct SweepArgs {
     // batched launches: blockIdx.y is the instance; its arrays, kinetic
     // table, stats slots and windows sit at these strides from instance 0's
     int grid_cap;               // persistent kernels: at most this many blocks along x
+    int row_ch;                 // fast row kernel: points per thread (4 or 8)
     int nb;                     // instances (1: plain plan)
     int64_t b_u;
     int64_t b_k;

@@ -35,7 +35,8 @@ def _dev_f64(t: torch.Tensor, name: str, shape=None) -> torch.Tensor:
 
 
 def make_desc(n: Sequence[int], tau: float, P: Sequence[float], period=None, method: str = "fast",
-              window=None, kstar_tabs=None, t0: float = 0.0, graph: bool = True, keep=None) -> LoDesc:
+              window=None, kstar_tabs=None, t0: float = 0.0, graph: bool = True, keep=None,
+              autotune: bool = False) -> LoDesc:
     ndim = len(n)
     d = LoDesc()
     d.ndim = ndim
@@ -53,7 +54,7 @@ def make_desc(n: Sequence[int], tau: float, P: Sequence[float], period=None, met
             d.kstar_half[a] = (tab.shape[0] - 1) // 2
     d.tau = float(tau)
     d.method = _lib.LO_FAST if method == "fast" else _lib.LO_BRUTE
-    d.flags = 0 if graph else _lib.LO_FLAG_NO_GRAPH
+    d.flags = (0 if graph else _lib.LO_FLAG_NO_GRAPH) | (_lib.LO_FLAG_AUTOTUNE if autotune else 0)
     d.t0 = float(t0)
     return d
 
@@ -64,19 +65,21 @@ class Plan:
     n: grid points per axis (axis 0 first).  V: static potential on the grid
     (CUDA float64 tensor shaped like the grid), or basis (CUDA tensor
     [M, *grid]) with static coef (M,) or time-dependent tcoef (steps, M).
+    autotune: the first run times the fast sweeps' launch shapes on a copy of
+    its input and keeps the fastest (results do not depend on the shape).
     """
 
     def __init__(self, n: Sequence[int], tau: float, P: Sequence[float], period=None,
                  V: Optional[torch.Tensor] = None, basis: Optional[torch.Tensor] = None,
                  coef=None, tcoef=None, method: str = "fast", window=None, kstar_tabs=None,
-                 t0: float = 0.0, graph: bool = True):
+                 t0: float = 0.0, graph: bool = True, autotune: bool = False):
         self.n = tuple(int(v) for v in n)
         self.ndim = len(self.n)
         self.shape = tuple(reversed(self.n))
         self.npts = int(np.prod(self.n))
         self.tau = float(tau)
         self._keep = []
-        desc = make_desc(self.n, tau, P, period, method, window, kstar_tabs, t0, graph, self._keep)
+        desc = make_desc(self.n, tau, P, period, method, window, kstar_tabs, t0, graph, self._keep, autotune)
         pot = LoPotential()
         self.V = None
         self.basis = None

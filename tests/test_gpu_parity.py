@@ -317,3 +317,20 @@ def test_fast_argmins_attain_the_value(torch_dev, orc, n, tau, P):
     same = got == ref
     assert same.mean() > 0.99
     assert np.array_equal(arg[:, same], rarg[:, same].astype(np.int64))
+
+
+@pytest.mark.parametrize("n,steps", [((512, 384), 40), ((96, 64, 80), 12), ((1000,), 30)])
+def test_autotuned_plan_is_bitwise_identical(torch_dev, n, steps):
+    """Launch shapes chosen by the tuner change speed, not values."""
+    torch = torch_dev
+    print_case("autotune", n)
+    u0 = wl.smooth_grid(list(n), 600)
+    V = wl.smooth_grid(list(n), 601)
+    P = [0.2, -0.3, 0.1][: len(n)]
+    outs = []
+    for tune in (False, True):
+        p = _plan(torch, n, 0.02, P, V, "fast", autotune=tune)
+        u = _gpu(torch, u0)
+        p.run(u, steps)
+        outs.append(u.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
