@@ -212,3 +212,25 @@ def test_config5_full_size_first_steps_vs_oracle(torch_dev, orc):
     _, gu, gc, _ = _run_adjoint(torch, w.n, w.tau, w.P, w.basis, w.coef, w.u0, gT, steps, 2, "fast")
     assert _rel(gu, gu_ref) <= ADJ_TOL, _rel(gu, gu_ref)
     assert _rel(gc, gc_ref) <= ADJ_TOL, _rel(gc, gc_ref)
+
+
+def test_autotuned_plan_same_gradients(torch_dev):
+    """The launch-shape tuner leaves the forward values and the adjoint unchanged."""
+    torch = torch_dev
+    from paper_1210_4090_amd.lo import Plan
+    n, tau, P, steps, every = (256, 192), 0.01, (0.3, 0.1), 24, 8
+    basis = _basis(n, 6, 71)
+    B = _gpu(torch, basis)
+    coef = np.random.default_rng(72).standard_normal(6) * 0.5
+    u0 = _gpu(torch, wl.smooth_grid(list(n), 73))
+    gT = _gpu(torch, np.random.default_rng(74).standard_normal(u0.shape))
+    res = []
+    for tune in (False, True):
+        p = Plan(n, tau, P, basis=B, coef=coef, method="fast", autotune=tune)
+        u = u0.clone()
+        ck = p.run(u, steps, 0, every)
+        gu, gc = p.backward(ck, steps, every, gT)
+        res.append((u.cpu().numpy(), gu.cpu().numpy(), gc))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][2], res[1][2])
