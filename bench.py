@@ -179,7 +179,7 @@ def measure_hbar(torch, method, subset=32):
             "subset_speedup_batched": t_loop / t_sub}
 
 
-def cpu_baseline(w, nsteps=12):
+def cpu_baseline(w, nsteps=30):
     from oracle import oracle
     t0 = time.perf_counter()
     oracle.run(w.u0, w.tau, w.P, nsteps, V=w.V)

@@ -162,7 +162,8 @@ lo_status lo_kinetic_table(lo_plan_t plan, int32_t axis, int64_t s0, int64_t cou
 /* Measurement aid: runs steps n0 .. n0+nsteps-1 on u (device [npts]) like
  * lo_run but without a graph, with HIP events on `stream` around every axis
  * sweep; ms (host [ndim]) receives the mean duration of each axis' kernel in
- * milliseconds.  Synchronous. */
+ * milliseconds, less the mean interval of an empty event pair recorded on the
+ * same stream each step.  Synchronous. */
 lo_status lo_time_kernels(lo_plan_t plan, double* u, int64_t n0, int64_t nsteps, double* ms, void* stream);
 
 #ifdef __cplusplus

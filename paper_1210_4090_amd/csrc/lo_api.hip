@@ -941,9 +941,12 @@ lo_status lo_time_kernels(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, do
     hipStream_t s = (hipStream_t)stream;
     lo_status st = prologue(p, u, n0, s);
     if (st) return st;
-    hipEvent_t ev[2 * kMaxDim];
-    for (int i = 0; i < 2 * p->ndim; i++) HIPCHK(hipEventCreate(&ev[i]));
-    double acc[kMaxDim] = {0, 0, 0};
+    // events around every sweep, and an empty pair each step whose interval
+    // (the events' own cost) is subtracted from the sweeps'
+    hipEvent_t ev[2 * kMaxDim + 2];
+    const int nev = 2 * p->ndim + 2;
+    for (int i = 0; i < nev; i++) HIPCHK(hipEventCreate(&ev[i]));
+    double acc[kMaxDim] = {0, 0, 0}, empty = 0.0;
     for (int64_t k = 0; k < nsteps && !st; k++) {
         if (k > 0 && k % kGraphSteps == 0) {
             st = adapt_from_flags(p, s);
@@ -951,7 +954,8 @@ lo_status lo_time_kernels(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, do
         }
         st = enqueue_step(p, u, n0 + k, nullptr, s, ev);
         if (st) break;
-        if (hipEventSynchronize(ev[2 * p->ndim - 1]) != hipSuccess) {
+        if (hipEventRecord(ev[nev - 2], s) != hipSuccess || hipEventRecord(ev[nev - 1], s) != hipSuccess ||
+            hipEventSynchronize(ev[nev - 1]) != hipSuccess) {
             st = LO_ERR_HIP;
             break;
         }
@@ -960,10 +964,13 @@ lo_status lo_time_kernels(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, do
             if (hipEventElapsedTime(&t, ev[2 * a], ev[2 * a + 1]) != hipSuccess) st = LO_ERR_HIP;
             acc[a] += t;
         }
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[nev - 2], ev[nev - 1]) != hipSuccess) st = LO_ERR_HIP;
+        empty += t;
     }
-    for (int i = 0; i < 2 * p->ndim; i++) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < nev; i++) (void)hipEventDestroy(ev[i]);
     if (st) return st;
-    for (int a = 0; a < p->ndim; a++) ms[a] = acc[a] / (double)nsteps;
+    for (int a = 0; a < p->ndim; a++) ms[a] = std::max(0.0, (acc[a] - empty) / (double)nsteps);
     return finish(p, s, false);
 }
 

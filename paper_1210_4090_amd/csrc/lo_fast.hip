@@ -529,8 +529,9 @@ hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double
     SweepArgs b = a;
     b.row_ch = row_ch;
     const ClaimLds L = claim_layout(a.kind, a.g.n, a.tile_rows, a.halo, a.argmin != nullptr, row_ch);
-    // ROW: persistent blocks, at most grid_cap along x, each walks several tiles
-    const int64_t cap = std::max(1, a.grid_cap);
+    // ROW: persistent blocks, about grid_cap in all (instances included), each
+    // walking several tiles so that its fixed costs are amortised
+    const int64_t cap = std::max(1, a.grid_cap / std::max(1, a.nb));
     if (a.kind == kKindRow) {
         const int64_t tiles = (a.g.nlines + L.nr - 1) / L.nr;
         return launch_claim_t<1>(in, out, b, L, inv2c, pofs, std::min(tiles, cap), s);
