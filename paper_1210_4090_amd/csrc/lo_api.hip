@@ -31,6 +31,7 @@ struct lo_plan_s {
     bool user_table[kMaxDim] = {false, false, false};
     int kind[kMaxDim] = {kKindRow, kKindTile, kKindTile};
     int halo[kMaxDim] = {0, 0, 0};       // halo of the next launches (adapted by lo_run)
+    int wseg[kMaxDim] = {0, 0, 0};       // widest window of the last segment (or the first step)
     int halo_max[kMaxDim] = {0, 0, 0};   // largest halo the LDS budget allows
     int tile_rows[kMaxDim] = {0, 0, 0};
     int tile_fix[kMaxDim] = {0, 0, 0};    // fast tiles: length chosen by the tuner (0: from the halo)
@@ -473,6 +474,7 @@ lo_status adapt_from_slot(lo_plan_t p, int64_t n0, hipStream_t s)
         win[2 * a + 1] = wm;
         p->hflags[1 + a] = std::max(p->hflags[1 + a], (uint32_t)std::max(wp, wm));
         p->halo[a] = choose_halo(p, a, std::max(wp, wm));
+        p->wseg[a] = std::max(wp, wm);
     }
     int* dst = p->win + (size_t)(((n0 % 2) + 2) % 2) * 2 * kMaxDim;
     HIPCHK(hipMemcpyAsync(dst, win, sizeof(win), hipMemcpyHostToDevice, s));
@@ -494,6 +496,7 @@ lo_status adapt_from_flags(lo_plan_t p, hipStream_t s)
         const uint32_t wu = fold_window(f, a);
         p->hflags[1 + a] = std::max(p->hflags[1 + a], wu);
         p->halo[a] = choose_halo(p, a, (int)wu);
+        p->wseg[a] = (int)wu;
     }
     // restart the per-segment window maxima (error bits and argmin maxima stay)
     HIPCHK(hipMemsetAsync(p->flags + kFlagWin, 0, sizeof(uint32_t) * 3 * kSpread, s));
@@ -887,9 +890,16 @@ lo_status lo_run(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckp
     st = prologue(p, u, n0, s);
     if (st) return st;
     const bool use_graph = graphable(p) && !ckpt;
+    // From smooth data (u0 = 0, say) the windows first widen by several points
+    // a step, more than the halos' slack covers over a whole segment.  While
+    // they grow, segments stay short (2, 4, 8, 16 steps), and the halos are
+    // sized for the growth the last segment predicts for the next.
+    int64_t warm = 2;
+    int wl[kMaxDim];
+    for (int a = 0; a < kMaxDim; a++) wl[a] = p->wseg[a];
     int64_t done = 0;
     while (done < nsteps) {
-        const int64_t seg = std::min<int64_t>(kGraphSteps, nsteps - done);
+        const int64_t seg = std::min<int64_t>(warm > 0 ? warm : kGraphSteps, nsteps - done);
         if (use_graph && seg == kGraphSteps) {
             hipGraphExec_t ge = nullptr;
             st = get_graph(p, u, n0 + done, &ge);
@@ -909,6 +919,17 @@ lo_status lo_run(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckp
         if (done < nsteps) {
             st = adapt_from_flags(p, s);
             if (st) return st;
+            if (warm > 0) {
+                const int64_t next = std::min<int64_t>(2 * warm, 16);
+                bool grows = false;
+                for (int a = 0; a < p->ndim; a++) {
+                    const int64_t d = (int64_t)p->wseg[a] - wl[a];
+                    if (d * kGraphSteps > 8 * seg) grows = true;   // would outgrow half the slack in a segment
+                    if (d > 0) p->halo[a] = choose_halo(p, a, (int)std::min<int64_t>(p->wseg[a] + d * next / seg, 1 << 30));
+                    wl[a] = p->wseg[a];
+                }
+                warm = grows ? next : 0;
+            }
         }
     }
     return finish(p, s, false);

@@ -23,13 +23,19 @@
 // sequences; this claim form is what turns the same convexity into
 // independent per-source work for a wavefront.)
 //
-// A minimiser lies within the step's window, so claims are clipped to the
-// staged part of the cost table (|t - j| <= KH); a clipped candidate is
-// never the minimum.  The kept value is a genuine candidate of the
+// A minimiser lies within the step's window, so claims are clipped to it; a
+// clipped candidate is never the minimum.  Costs come from a band of 2 KH + 1
+// consecutive offsets of the table staged in LDS (KH is the plan's halo),
+// starting at the window's low end, so an asymmetric window (a large |P|
+// shifts the minimisers) fits whenever its width does.  A wider window is
+// claimed band by band, restaging the table between bands (minima over the
+// union of the candidates are the same), in chunks of two sources so that this
+// rare path needs fewer registers than the main one.  The kept value is a genuine candidate of the
 // definition and equals the exhaustive minimum except where two candidates
 // differ by a few ulps.  Ties are broken by a second pass that keeps the
 // smallest offset (lowest lifted source) among the claimants attaining the
-// minimum.  Windows beyond the staged table fall back to the exhaustive loop.
+// minimum.  Row sweeps whose window reaches a whole row fall back to the
+// exhaustive loop.
 //
 // Work layout: a thread takes chunks of kCh consecutive sources of one line,
 // loads the kCh + 2 values around them once, and computes every crossing once.
@@ -73,7 +79,7 @@ struct ClaimLds {
     int nr;      // ROW: rows per tile
     int RS;      // ROW: skewed key slots of a tile
     int NT;      // TILE: targets per line (R + 1)
-    int KH;      // staged cost table covers |s| <= KH
+    int KH;      // staged cost table: a band of 2 KH + 1 offsets
 };
 
 __host__ __device__ inline size_t claim_lds_bytes(const ClaimLds& f)
@@ -93,14 +99,15 @@ namespace {
 
 // Claims of one chunk: sources p0 .. min(p0 + kCh - 1, plast) (lifted) of one
 // line with uu[k] = u(p0 - 1 + k), k = 0 .. kCh + 1.  Targets are clipped to
-// [tmin, tmax] (lifted) and to |t - p| <= KH; key(t) gives the LDS slot of
-// lifted target t.  PASS 0: atomic minimum of the candidate into W;
-// PASS 1: among the candidates equal to W, atomic minimum of the offset
+// [tmin, tmax] (lifted) and to t - p in [smin, smax], a range the centred cost
+// table K (LDS or global; K[s] = k(s)) covers; key(t) gives the LDS slot of
+// lifted target t.  PASS 0: atomic minimum of the candidate into W; PASS 1:
+// among the candidates equal to W, atomic minimum of the offset
 // (source - target) into A.
 template <int PASS, int CH, typename KeyOf>
 __device__ __forceinline__ void claim_chunk(const double (&uu)[CH + 2], int p0, int plast, int tmin, int tmax,
-                                            const double* KT, int KH, double inv2c, double pofs, double* W,
-                                            int* A, KeyOf key)
+                                            int smin, int smax, const double* K, double inv2c, double pofs,
+                                            double* W, int* A, KeyOf key)
 {
     // crossing k lies between sources p0 - 1 + k and p0 + k
     int lo[CH + 1], hi[CH + 1];
@@ -116,11 +123,11 @@ __device__ __forceinline__ void claim_chunk(const double (&uu)[CH + 2], int p0, 
     for (int k = 0; k < CH; k++) {
         const int p = p0 + k;
         if (p > plast) break;
-        const int tlo = max(max(lo[k], p - KH - 1), tmin - 1) + 1;
-        const int thi = min(min(hi[k + 1], p + KH), tmax);
+        const int tlo = max(max(lo[k], p + smin - 1), tmin - 1) + 1;
+        const int thi = min(min(hi[k + 1], p + smax), tmax);
         const double up = uu[k + 1];
         for (int t = tlo; t <= thi; t++) {
-            const double v = up + KT[KH + t - p];
+            const double v = up + K[t - p];
             const int s = key(t);
             if (PASS == 0)
                 atomicMin(&W[s], v);
@@ -171,11 +178,13 @@ __device__ __forceinline__ void publish_stats(SweepStats& st, const SweepArgs& a
 // the tile: it loads them with 16-byte loads, claims for them as sources and
 // writes them as targets.  Keys live in LDS in the skewed layout; claims wrap
 // around the row.  Persistent: a block walks tiles blockIdx.x, + gridDim.x, ...
+// The plain sweep (no epilogue, no argmins) is held to 128 registers (it fits
+// without spilling): four waves a SIMD.
 // ---------------------------------------------------------------------------
 template <int EPI, int ARG, int CH, int BS>
-__global__ __launch_bounds__(BS) void k_claim_row(const double* __restrict__ in, double* __restrict__ out,
-                                                      const double* __restrict__ kc, SweepArgs a, ClaimLds L,
-                                                      double inv2c, double pofs)
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(CH == 8 && !ARG && !EPI ? 4 : 1))) void
+k_claim_row(const double* __restrict__ in, double* __restrict__ out, const double* __restrict__ kc, SweepArgs a,
+            ClaimLds L, double inv2c, double pofs)
 {
     extern __shared__ double sm[];
     __shared__ double red[40];
@@ -203,12 +212,21 @@ __global__ __launch_bounds__(BS) void k_claim_row(const double* __restrict__ in,
     int wm = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis + 1];
     wp = __builtin_amdgcn_readfirstlane(wp);
     wm = __builtin_amdgcn_readfirstlane(wm);
+    // the minimisers of the step lie within its window: claims are clipped to
+    // t - p in [-wm - 1, wp + 1] (offsets beyond the table's end cost +inf and
+    // never win)
+    const int kcap = (int)min((int64_t)a.kin.kcap, (int64_t)0x7fffffff);
+    const int smin = max(-wm - 1, -kcap), smax = min(wp + 1, kcap);
+    // KT[i] = k(smin + i), i < 2 KH + 1: the window's band
     for (int i = threadIdx.x; i < 2 * KH + 1; i += BS) {
-        const int s = i - KH;
-        KT[i] = (s >= -a.kin.kcap && s <= a.kin.kcap) ? kc[s] : INFINITY;
+        const int s = smin + i;
+        KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
     }
-    // claims reach |t - p| <= W + 1 for the minimisers; one wrap needs KH < N
-    const bool fast = wp + 1 <= KH && wm + 1 <= KH && KH < N;
+    // claims wrap once around the row (targets t of sources 0 .. N - 1 lie in
+    // [smin, N - 1 + smax]); the main path needs the window inside the band
+    const bool wraps = wp + 1 < N && wm + 1 < N;
+    const bool fast = wraps && smax - smin <= 2 * KH;
+    const double* K = KT - smin;   // K[s] = k(s), s in [smin, smax]
     const int kbase = r * N;
     auto key = [N, kbase](int t) { return skc<CH>(kbase + (t < 0 ? t + N : (t >= N ? t - N : t))); };
 
@@ -216,95 +234,183 @@ __global__ __launch_bounds__(BS) void k_claim_row(const double* __restrict__ in,
     int amax = 0;
     bool bad = false;
     const int64_t ntiles = (a.g.nlines + nr - 1) / nr;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t row = tile * nr + r;
-        const bool ok = act && row < a.g.nlines;
-        const double* __restrict__ src = in + row * N;
-        double uu[CH + 2];
-        if (ok) {
-            uu[0] = src[p0 == 0 ? N - 1 : p0 - 1];
-            const double2* s2 = (const double2*)(src + p0);
+    // outputs, argmins and statistics of one tile row from the keys
+    auto emit = [&](int64_t row, bool ok) {
+        if (!ok) return;
+        double x[CH + 1];
+#pragma unroll
+        for (int k = 0; k < CH; k++) x[k] = W[skc<CH>(g0 + k)];
+        x[CH] = W[skc<CH>(kbase + (p0 + CH == N ? 0 : p0 + CH))];
+        double z[CH];
+        if (EPI) {
+            const double2* h2 = (const double2*)(a.hv + row * N + p0);
 #pragma unroll
             for (int k = 0; k < CH / 2; k++) {
-                const double2 v = s2[k];
-                uu[1 + 2 * k] = v.x;
-                uu[2 + 2 * k] = v.y;
-            }
-            uu[CH + 1] = src[p0 + CH == N ? 0 : p0 + CH];
-#pragma unroll
-            for (int k = 0; k < CH; k++) {
-                W[skc<CH>(g0 + k)] = INFINITY;
-                if (ARG) A[skc<CH>(g0 + k)] = 0x7fffffff;
-            }
-        }
-        __syncthreads();
-        if (fast) {
-            if (ok) claim_chunk<0, CH>(uu, p0, N - 1, -KH, N - 1 + KH, KT, KH, inv2c, pofs, W, A, key);
-            __syncthreads();
-            if (ARG) {
-                if (ok) claim_chunk<1, CH>(uu, p0, N - 1, -KH, N - 1 + KH, KT, KH, inv2c, pofs, W, A, key);
-                __syncthreads();
+                const double2 v = h2[k];
+                z[2 * k] = x[2 * k] - v.x;
+                z[2 * k + 1] = x[2 * k + 1] - v.y;
             }
         } else {
-            // exhaustive window over the wrapped row, sources from global memory
+#pragma unroll
+            for (int k = 0; k < CH; k++) z[k] = x[k];
+        }
+        double2* d2 = (double2*)(out + row * N + p0);
+#pragma unroll
+        for (int k = 0; k < CH / 2; k++) d2[k] = make_double2(z[2 * k], z[2 * k + 1]);
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            bad |= !(x[k] < INFINITY);
+            if (a.stats_out) fold_stats<EPI>(st, x[k], x[k + 1], z[k]);
+        }
+        if (ARG && a.argmin) {
+            int16_t* am = a.argmin + row * N + p0;
+#pragma unroll
+            for (int k = 0; k < CH; k++) {
+                const int e = A[skc<CH>(g0 + k)];
+                am[k] = (int16_t)e;
+                amax = max(amax, abs(e));
+            }
+        }
+    };
+    if (wraps && !fast) {
+        // window wider than the band: band by band, chunks of two sources, in a
+        // loop of its own (its registers stay apart from the main loop's)
+        for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+            const int64_t row = tile * nr + r;
+            const bool ok = act && row < a.g.nlines;
+            const double* __restrict__ src = in + row * N;
             if (ok) {
+#pragma unroll
                 for (int k = 0; k < CH; k++) {
-                    const int t = p0 + k;
-                    double best = INFINITY;
-                    int arg = 0;
-                    int j = (t - wp) % N;
-                    if (j < 0) j += N;
-                    for (int e = -wp; e <= wm; ++e) {
-                        const double v = src[j] + kc[-e];
-                        if (v < best) {
-                            best = v;
-                            arg = e;
-                        }
-                        if (++j == N) j = 0;
+                    W[skc<CH>(g0 + k)] = INFINITY;
+                    if (ARG) A[skc<CH>(g0 + k)] = 0x7fffffff;
+                }
+            }
+            for (int pass = 0; pass < (ARG ? 2 : 1); pass++) {
+                for (int blo = smin; blo <= smax; blo += 2 * KH + 1) {
+                    const int bhi = min(blo + 2 * KH, smax);
+                    __syncthreads();
+                    for (int i = threadIdx.x; i < 2 * KH + 1; i += BS) {
+                        const int s = blo + i;
+                        KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
                     }
-                    W[skc<CH>(g0 + k)] = best;
-                    if (ARG) A[skc<CH>(g0 + k)] = arg;
+                    __syncthreads();
+                    if (ok) {
+#pragma unroll 1
+                        for (int k = 0; k < CH; k += 2) {
+                            // reloaded (not the registers above): keeps this path's registers low
+                            double u4[4];
+                            int j = p0 + k == 0 ? N - 1 : p0 + k - 1;
+#pragma unroll
+                            for (int i = 0; i < 4; i++) {
+                                u4[i] = src[j];
+                                j = j + 1 == N ? 0 : j + 1;
+                            }
+                            if (pass == 0)
+                                claim_chunk<0, 2>(u4, p0 + k, N - 1, smin, N - 1 + smax, blo, bhi, KT - blo, inv2c,
+                                                  pofs, W, A, key);
+                            else
+                                claim_chunk<1, 2>(u4, p0 + k, N - 1, smin, N - 1 + smax, blo, bhi, KT - blo, inv2c,
+                                                  pofs, W, A, key);
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            emit(row, ok);
+            __syncthreads();   // keys are reused by the next tile
+        }
+    } else {
+        for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+            const int64_t row = tile * nr + r;
+            const bool ok = act && row < a.g.nlines;
+            const double* __restrict__ src = in + row * N;
+            double uu[CH + 2];
+            if (ok) {
+                uu[0] = src[p0 == 0 ? N - 1 : p0 - 1];
+                const double2* s2 = (const double2*)(src + p0);
+#pragma unroll
+                for (int k = 0; k < CH / 2; k++) {
+                    const double2 v = s2[k];
+                    uu[1 + 2 * k] = v.x;
+                    uu[2 + 2 * k] = v.y;
+                }
+                uu[CH + 1] = src[p0 + CH == N ? 0 : p0 + CH];
+#pragma unroll
+                for (int k = 0; k < CH; k++) {
+                    W[skc<CH>(g0 + k)] = INFINITY;
+                    if (ARG) A[skc<CH>(g0 + k)] = 0x7fffffff;
                 }
             }
             __syncthreads();
-        }
-        if (ok) {
-            double x[CH + 1];
-#pragma unroll
-            for (int k = 0; k < CH; k++) x[k] = W[skc<CH>(g0 + k)];
-            x[CH] = W[skc<CH>(kbase + (p0 + CH == N ? 0 : p0 + CH))];
-            double z[CH];
-            if (EPI) {
-                const double2* h2 = (const double2*)(a.hv + row * N + p0);
-#pragma unroll
-                for (int k = 0; k < CH / 2; k++) {
-                    const double2 v = h2[k];
-                    z[2 * k] = x[2 * k] - v.x;
-                    z[2 * k + 1] = x[2 * k + 1] - v.y;
+            if (fast) {
+                if (ok) claim_chunk<0, CH>(uu, p0, N - 1, smin, N - 1 + smax, smin, smax, K, inv2c, pofs, W, A, key);
+                __syncthreads();
+                if (ARG) {
+                    if (ok) claim_chunk<1, CH>(uu, p0, N - 1, smin, N - 1 + smax, smin, smax, K, inv2c, pofs, W, A, key);
+                    __syncthreads();
                 }
             } else {
-#pragma unroll
-                for (int k = 0; k < CH; k++) z[k] = x[k];
+                // exhaustive window over the wrapped row, sources from global memory
+                if (ok) {
+                    for (int k = 0; k < CH; k++) {
+                        const int t = p0 + k;
+                        double best = INFINITY;
+                        int arg = 0;
+                        int j = (t - wp) % N;
+                        if (j < 0) j += N;
+                        for (int e = -wp; e <= wm; ++e) {
+                            const double v = src[j] + kc[-e];
+                            if (v < best) {
+                                best = v;
+                                arg = e;
+                            }
+                            if (++j == N) j = 0;
+                        }
+                        W[skc<CH>(g0 + k)] = best;
+                        if (ARG) A[skc<CH>(g0 + k)] = arg;
+                    }
+                }
+                __syncthreads();
             }
-            double2* d2 = (double2*)(out + row * N + p0);
+            if (ok) {
+                double x[CH + 1];
 #pragma unroll
-            for (int k = 0; k < CH / 2; k++) d2[k] = make_double2(z[2 * k], z[2 * k + 1]);
+                for (int k = 0; k < CH; k++) x[k] = W[skc<CH>(g0 + k)];
+                x[CH] = W[skc<CH>(kbase + (p0 + CH == N ? 0 : p0 + CH))];
+                double z[CH];
+                if (EPI) {
+                    const double2* h2 = (const double2*)(a.hv + row * N + p0);
 #pragma unroll
-            for (int k = 0; k < CH; k++) {
-                bad |= !(x[k] < INFINITY);
-                if (a.stats_out) fold_stats<EPI>(st, x[k], x[k + 1], z[k]);
-            }
-            if (ARG && a.argmin) {
-                int16_t* am = a.argmin + row * N + p0;
+                    for (int k = 0; k < CH / 2; k++) {
+                        const double2 v = h2[k];
+                        z[2 * k] = x[2 * k] - v.x;
+                        z[2 * k + 1] = x[2 * k + 1] - v.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < CH; k++) z[k] = x[k];
+                }
+                double2* d2 = (double2*)(out + row * N + p0);
+#pragma unroll
+                for (int k = 0; k < CH / 2; k++) d2[k] = make_double2(z[2 * k], z[2 * k + 1]);
 #pragma unroll
                 for (int k = 0; k < CH; k++) {
-                    const int e = A[skc<CH>(g0 + k)];
-                    am[k] = (int16_t)e;
-                    amax = max(amax, abs(e));
+                    bad |= !(x[k] < INFINITY);
+                    if (a.stats_out) fold_stats<EPI>(st, x[k], x[k + 1], z[k]);
+                }
+                if (ARG && a.argmin) {
+                    int16_t* am = a.argmin + row * N + p0;
+#pragma unroll
+                    for (int k = 0; k < CH; k++) {
+                        const int e = A[skc<CH>(g0 + k)];
+                        am[k] = (int16_t)e;
+                        amax = max(amax, abs(e));
+                    }
                 }
             }
+            __syncthreads();   // keys are reused by the next tile
         }
-        __syncthreads();   // keys are reused by the next tile
     }
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
     if (ARG && a.argmin) {
@@ -365,10 +471,16 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
     wp = __builtin_amdgcn_readfirstlane(wp);
     wm = __builtin_amdgcn_readfirstlane(wm);
 
+    // offsets beyond the table's end cost +inf and never win
+    const int kcap = (int)min((int64_t)a.kin.kcap, (int64_t)0x7fffffff);
+    const int smin = max(-wm - 1, -kcap), smax = min(wp + 1, kcap);
+    // KT[i] = k(smin + i), i < 2 KH + 1: the window's band
     for (int i = threadIdx.x; i < 2 * KH + 1; i += kBlock) {
-        const int s = i - KH;
-        KT[i] = (s >= -a.kin.kcap && s <= a.kin.kcap) ? kc[s] : INFINITY;
+        const int s = smin + i;
+        KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
     }
+    const bool fast = smax - smin <= 2 * KH;
+    const double* K = KT - smin;   // K[s] = k(s), s in [smin, smax]
     for (int t = q; t < NT; t += kBlock / C) {
         W[t * kKeyStride + c] = INFINITY;
         if (ARG) A[t * kKeyStride + c] = 0x7fffffff;
@@ -376,7 +488,6 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
     __syncthreads();
 
     const double* __restrict__ src = in + lbase;
-    const bool fast = wp + 1 <= KH && wm + 1 <= KH;
     if (fast) {
         // sources that can reach the targets: [r0 - wp, r0 + NT - 1 + wm]
         const int pA = r0 - wp, pB = r0 + NT - 1 + wm;
@@ -394,31 +505,47 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
                 }
                 auto key = [r0](int t) { return (t - r0) * kKeyStride; };
                 if (pass == 0)
-                    claim_chunk<0, kCh>(uu, p0, pB, r0, r0 + NT - 1, KT, KH, inv2c, pofs, W + c, A + c, key);
+                    claim_chunk<0, kCh>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, W + c, A + c, key);
                 else
-                    claim_chunk<1, kCh>(uu, p0, pB, r0, r0 + NT - 1, KT, KH, inv2c, pofs, W + c, A + c, key);
+                    claim_chunk<1, kCh>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, W + c, A + c, key);
             }
             __syncthreads();
         }
     } else {
-        // exhaustive window straight from global memory
-        for (int t = q; t < NT && lok; t += kBlock / C) {
-            double best = INFINITY;
-            int arg = 0;
-            int j = (r0 + t - wp) % N;
-            if (j < 0) j += N;
-            for (int e = -wp; e <= wm; ++e) {
-                const double v = src[(int64_t)S * j] + kc[-e];
-                if (v < best) {
-                    best = v;
-                    arg = e;
+        // window wider than the band: band by band, chunks of two sources
+        for (int pass = 0; pass < (ARG ? 2 : 1); pass++) {
+            for (int blo = smin; blo <= smax; blo += 2 * KH + 1) {
+                const int bhi = min(blo + 2 * KH, smax);
+                __syncthreads();
+                for (int i = threadIdx.x; i < 2 * KH + 1; i += kBlock) {
+                    const int s = blo + i;
+                    KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
                 }
-                if (++j == N) j = 0;
+                __syncthreads();
+                // sources that reach the targets with an offset of the window and of the band
+                const int pA = max(r0 - wp, r0 - bhi), pB = min(r0 + NT - 1 + wm, r0 + NT - 1 - blo);
+                const int nch = (pB - pA + 2) / 2;
+                for (int ch = q; ch < nch && lok; ch += kBlock / C) {
+                    const int p0 = pA + 2 * ch;
+                    double u4[4];
+                    int r = (p0 - 1) % N;
+                    if (r < 0) r += N;
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        u4[k] = src[S * r];
+                        r = r + 1 == N ? 0 : r + 1;
+                    }
+                    auto key = [r0](int t) { return (t - r0) * kKeyStride; };
+                    if (pass == 0)
+                        claim_chunk<0, 2>(u4, p0, pB, r0, r0 + NT - 1, blo, bhi, KT - blo, inv2c, pofs, W + c, A + c,
+                                          key);
+                    else
+                        claim_chunk<1, 2>(u4, p0, pB, r0, r0 + NT - 1, blo, bhi, KT - blo, inv2c, pofs, W + c, A + c,
+                                          key);
+                }
             }
-            W[t * kKeyStride + c] = best;
-            if (ARG) A[t * kKeyStride + c] = arg;
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // ---- outputs, argmins, stats of this sweep's result ----

@@ -334,3 +334,30 @@ def test_autotuned_plan_is_bitwise_identical(torch_dev, n, steps):
         p.run(u, steps)
         outs.append(u.cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("argmin", [False, True])
+def test_fast_window_wider_than_the_staged_band(torch_dev, orc, argmin):
+    """Fixed windows wider than any staged band of the cost table: 600 points
+    on the 2048-point rows (bands of at most 2 x 512 + 1 offsets) and 70 on
+    the 40-point axis (bands of 2 x 40 + 1): row and tile sweeps claim band by
+    band.  Values within 1e-12 of the
+    oracle; argmins equal the oracle's wherever the values agree."""
+    torch = torch_dev
+    n, tau, P = (2048, 40), 0.02, (0.2, -0.3)
+    print_case("band by band", n, argmin)
+    u0 = wl.smooth_grid(list(n), 700) + 0.05 * wl.random_grid(list(n), 701)
+    V = wl.smooth_grid(list(n), 702)
+    p = _plan(torch, n, tau, P, V, "fast", window=[600, 70])
+    u = _gpu(torch, u0)
+    if argmin:
+        arg = p.step(u, 0, argmin=True).cpu().numpy().astype(np.int64)
+        ref, rarg = orc.step(u0, tau, P, V=V, with_argmin=True)
+        got = u.cpu().numpy()
+        _check(got, ref, "fast")
+        same = got == ref
+        assert same.mean() > 0.99
+        assert np.array_equal(arg[:, same], rarg[:, same].astype(np.int64))
+    else:
+        p.run(u, 4)
+        _check(u.cpu().numpy(), orc.run(u0, tau, P, 4, V=V), "fast")
