@@ -301,6 +301,12 @@ lo_status setup_potential(lo_plan_t p, const lo_potential* V)
     return LO_OK;
 }
 
+// Lines side by side in axis a's fast tiles, and the tile length: a tile of one
+// line (an axis with fewer than 16 lines) is 4x longer, so that a block still
+// has as many targets.
+int tile_lines_of(lo_plan_t p, int a) { return fast_tile_lines(p->npts / p->n[a]); }
+int tile_len(lo_plan_t p, int a, bool wide) { return (wide ? 256 : 128) * (tile_lines_of(p, a) == 1 ? 4 : 1); }
+
 void choose_kernels(lo_plan_t p)
 {
     int dev = 0, lds_max = 65536;
@@ -320,14 +326,14 @@ void choose_kernels(lo_plan_t p)
         p->fast[a] = fast && !p->user_table[a];
         // fast: whole rows of a multiple of 8 points for axis 0, tiles otherwise
         const bool row_ok = a == 0 && N <= 2048 &&
-                            (p->fast[a] ? N % 8 == 0 && fast_lds_for(kKindRow, N, 0, 1) <= fbudget
+                            (p->fast[a] ? N % 8 == 0 && fast_lds_for(kKindRow, N, 0, 1, 1) <= fbudget
                                         : row_lds_bytes(N, 8) <= budget);
         if (row_ok) {
             p->kind[a] = kKindRow;
             // the fast row kernel wraps claims once around the row: its cost table stays below N
             int64_t H = p->fast[a] ? std::min<int64_t>(N - 1, 512) : std::min<int64_t>(N, 1024);
             if (p->fast[a])
-                while (H > 1 && fast_lds_for(kKindRow, N, 0, (int)H) > fbudget) H = H * 7 / 8;
+                while (H > 1 && fast_lds_for(kKindRow, N, 0, (int)H, 1) > fbudget) H = H * 7 / 8;
             else
                 while (H > 8 && row_lds_bytes(N, (int)H) > budget) H = H * 7 / 8;
             p->halo[a] = (int)std::max<int64_t>(H, 1);
@@ -335,10 +341,10 @@ void choose_kernels(lo_plan_t p)
             p->tile_rows[a] = 0;
         } else {
             p->kind[a] = kKindTile;
-            int R = p->fast[a] ? 256 : (int)std::min<int64_t>(N, 128);
+            int R = p->fast[a] ? tile_len(p, a, true) : (int)std::min<int64_t>(N, 128);
             int H = (int)std::min<int64_t>(N, p->fast[a] ? 512 : 256);
             if (p->fast[a])
-                while (H > 8 && fast_lds_for(kKindTile, N, R, H) > fbudget) H -= 4;
+                while (H > 8 && fast_lds_for(kKindTile, N, R, H, tile_lines_of(p, a)) > fbudget) H -= 4;
             else
                 while (H > 8 && tile_lds_bytes(H) > budget) H -= 8;
             p->tile_rows[a] = R;
@@ -433,7 +439,8 @@ int choose_halo(lo_plan_t p, int a, int W)
     H = std::max(8, std::min(H, p->halo_max[a]));
     // fast tiles: longer tiles when the window's halo is wide (fewer halo
     // sources per target), shorter ones keep more blocks resident otherwise
-    if (p->fast[a] && p->kind[a] == kKindTile) p->tile_rows[a] = p->tile_fix[a] > 0 ? p->tile_fix[a] : (H >= 40 ? 256 : 128);
+    if (p->fast[a] && p->kind[a] == kKindTile)
+        p->tile_rows[a] = p->tile_fix[a] > 0 ? p->tile_fix[a] : tile_len(p, a, H >= 40);
     return H;
 }
 
@@ -651,7 +658,7 @@ lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
         lo_status st = alloc((void**)&p->tune_u, bytes);
         if (st) return st;
     }
-    static const int kR[2] = {128, 256}, kC[2] = {8, 4};
+    static const int kC[2] = {8, 4};
     double ms[2][2][kMaxDim] = {};
     hipEvent_t ev[2 * kMaxDim];
     for (int i = 0; i < 2 * p->ndim; i++) HIPCHK(hipEventCreate(&ev[i]));
@@ -659,7 +666,7 @@ lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
     for (int ci = 0; ci < 2 && !st; ci++) {
         for (int ri = 0; ri < 2 && !st; ri++) {
             for (int a = 0; a < p->ndim; a++) {
-                if (p->kind[a] == kKindTile) p->tile_fix[a] = kR[ri];
+                if (p->kind[a] == kKindTile) p->tile_fix[a] = tile_len(p, a, ri == 1);
                 else p->row_ch[a] = kC[ci];
             }
             if (hipMemcpyAsync(p->tune_u, u, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) st = LO_ERR_HIP;
@@ -681,7 +688,7 @@ lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
     for (int a = 0; a < p->ndim; a++) {
         if (p->kind[a] == kKindTile) {
             const double t128 = ms[0][0][a] + ms[1][0][a], t256 = ms[0][1][a] + ms[1][1][a];
-            p->tile_fix[a] = t256 < t128 ? 256 : 128;
+            p->tile_fix[a] = tile_len(p, a, t256 < t128);
         } else {
             const double c8 = ms[0][0][a] + ms[0][1][a], c4 = ms[1][0][a] + ms[1][1][a];
             p->row_ch[a] = c4 < c8 ? 4 : 8;

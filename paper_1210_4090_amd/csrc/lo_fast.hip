@@ -61,8 +61,7 @@ namespace {
 using namespace dev;
 constexpr int kCh = 8;           // sources per chunk (tile kernel)
 constexpr int kRowPoints = 2048; // row kernel: points per tile (points per thread x threads)
-constexpr int kTileLines = 16;   // TILE: lines side by side
-constexpr int kKeyStride = kTileLines + 1;   // TILE key row stride (doubles)
+constexpr int kTileLines = 16;   // TILE: lines side by side (1 for axes with fewer lines)
 constexpr double kEps = 1e-6;    // claim widening, in cells
 
 // skewed LDS slot of key x for chunks of CH points: one pad slot per chunk,
@@ -72,6 +71,10 @@ __device__ __forceinline__ int skc(int x) { return x + x / CH; }
 
 }  // namespace
 
+// TILE key row stride in doubles: one pad slot per row of 16 lines (distinct
+// banks for the lines), none for a single line.
+__host__ __device__ constexpr int tile_key_stride(int C) { return C == 1 ? 1 : C + 1; }
+
 // Layout of the dynamic LDS of the claim kernels.
 struct ClaimLds {
     int arg;     // argmin array present
@@ -79,6 +82,7 @@ struct ClaimLds {
     int nr;      // ROW: rows per tile
     int RS;      // ROW: skewed key slots of a tile
     int NT;      // TILE: targets per line (R + 1)
+    int C;       // TILE: lines side by side (kTileLines, or 1)
     int KH;      // staged cost table: a band of 2 KH + 1 offsets
 };
 
@@ -89,8 +93,8 @@ __host__ __device__ inline size_t claim_lds_bytes(const ClaimLds& f)
         b += sizeof(double) * (size_t)f.RS;                                   // keys
         if (f.arg) b += sizeof(int) * (size_t)f.RS;                           // argmins
     } else {
-        b += sizeof(double) * (size_t)f.NT * kKeyStride;                     // keys
-        if (f.arg) b += sizeof(int) * (size_t)f.NT * kKeyStride;
+        b += sizeof(double) * (size_t)f.NT * tile_key_stride(f.C);           // keys
+        if (f.arg) b += sizeof(int) * (size_t)f.NT * tile_key_stride(f.C);
     }
     return (b + 15) & ~(size_t)15;
 }
@@ -422,10 +426,11 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
 }
 
 // ---------------------------------------------------------------------------
-// TILE kernel: 16 lines side by side x R targets [r0, r0 + R) (+ target
+// TILE kernel: C lines side by side (16, or 1 for an axis with fewer lines:
+// then the whole block works on one line) x R targets [r0, r0 + R) (+ target
 // r0 + R for the forward differences of the output), lines of any stride.
 // ---------------------------------------------------------------------------
-template <int EPI, int ARG>
+template <int EPI, int ARG, int C>
 __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict__ in, double* __restrict__ out,
                                                        const double* __restrict__ kc, SweepArgs a, ClaimLds L,
                                                        double inv2c, double pofs)
@@ -440,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
         kc += ko;
         if (a.pofs_b) pofs = a.pofs;
     }
-    constexpr int C = kTileLines;
+    constexpr int kKeyStride = tile_key_stride(C);
     const int N = (int)a.g.n;
     const int S = (int)a.g.stride;   // line offsets fit 32 bits (the plan caps the grid at 2^31 points)
     const int R = a.tile_rows;
@@ -580,9 +585,10 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
     maybe_next_windows(a);   // after this block's own work: off the critical path
 }
 
-ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg, int row_ch)
+ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg, int row_ch, int tile_lines)
 {
     ClaimLds L;
+    L.C = 1;
     L.arg = arg ? 1 : 0;
     L.KH = H;
     if (kind == kKindRow) {
@@ -596,6 +602,7 @@ ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg, int r
         L.nr = 1;
         L.RS = 0;
         L.NT = tile_rows + 1;
+        L.C = tile_lines;
     }
     return L;
 }
@@ -607,9 +614,15 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
     const size_t lds = claim_lds_bytes(L);
     const bool arg = a.argmin != nullptr;
     const bool epi = a.hv != nullptr;
-#define LO_CLAIM_LAUNCH(K, E, A)                                                                             \
-    hipLaunchKernelGGL((K<E, A>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out, a.kin.k, a, L, \
-                       inv2c, pofs)
+#define LO_CLAIM_LAUNCH(K, E, A)                                                                              \
+    do {                                                                                                        \
+        if (L.C == 1)                                                                                           \
+            hipLaunchKernelGGL((K<E, A, 1>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out, a.kin.k, \
+                               a, L, inv2c, pofs);                                                              \
+        else                                                                                                    \
+            hipLaunchKernelGGL((K<E, A, kTileLines>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out, \
+                               a.kin.k, a, L, inv2c, pofs);                                                     \
+    } while (0)
 #define LO_ROW_LAUNCH_CH(E, A, CH)                                                                            \
     hipLaunchKernelGGL((k_claim_row<E, A, CH, kRowPoints / CH>), dim3((unsigned)grid, a.nb),                  \
                        dim3(kRowPoints / CH), lds, s, in, out, a.kin.k, a, L, inv2c, pofs)
@@ -643,9 +656,11 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
 
 }  // namespace
 
-size_t fast_lds_for(int kind, int64_t N, int tile_rows, int H)
+int fast_tile_lines(int64_t nlines) { return nlines < kTileLines ? 1 : kTileLines; }
+
+size_t fast_lds_for(int kind, int64_t N, int tile_rows, int H, int tile_lines)
 {
-    return claim_lds_bytes(claim_layout(kind, N, tile_rows, H, true, 4));   // the larger row layout
+    return claim_lds_bytes(claim_layout(kind, N, tile_rows, H, true, 4, tile_lines));   // the larger row layout
 }
 
 hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double cq, double inv2c, double pofs,
@@ -655,7 +670,8 @@ hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double
     const int row_ch = a.row_ch == 4 ? 4 : 8;
     SweepArgs b = a;
     b.row_ch = row_ch;
-    const ClaimLds L = claim_layout(a.kind, a.g.n, a.tile_rows, a.halo, a.argmin != nullptr, row_ch);
+    const int C = fast_tile_lines(a.g.nlines);
+    const ClaimLds L = claim_layout(a.kind, a.g.n, a.tile_rows, a.halo, a.argmin != nullptr, row_ch, C);
     // ROW: persistent blocks, about grid_cap in all (instances included), each
     // walking several tiles so that its fixed costs are amortised
     const int64_t cap = std::max(1, a.grid_cap / std::max(1, a.nb));
@@ -663,7 +679,7 @@ hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double
         const int64_t tiles = (a.g.nlines + L.nr - 1) / L.nr;
         return launch_claim_t<1>(in, out, b, L, inv2c, pofs, std::min(tiles, cap), s);
     }
-    const int64_t tiles = ((a.g.n + a.tile_rows - 1) / a.tile_rows) * ((a.g.nlines + kTileLines - 1) / kTileLines);
+    const int64_t tiles = ((a.g.n + a.tile_rows - 1) / a.tile_rows) * ((a.g.nlines + C - 1) / C);
     return launch_claim_t<0>(in, out, b, L, inv2c, pofs, tiles, s);
 }
 

@@ -137,7 +137,8 @@ hipError_t launch_sweep(int method, const double* in, double* out, const SweepAr
 
 hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double cq, double inv2c,
                        double pofs, hipStream_t s);
-size_t fast_lds_for(int kind, int64_t N, int tile_rows, int H);
+size_t fast_lds_for(int kind, int64_t N, int tile_rows, int H, int tile_lines);
+int fast_tile_lines(int64_t nlines);   // lines side by side in a fast TILE sweep
 void row_layout(int64_t N, int halo, int* nr, int* RS, int* H);
 size_t row_lds_bytes(int64_t N, int halo);
 size_t tile_lds_bytes(int halo);

@@ -138,6 +138,7 @@ class Workload:
     period: Tuple[float, ...] = None
     basis: Optional[np.ndarray] = None      # (M, *grid) Fourier basis, if V = sum c_m phi_m
     coef: Optional[np.ndarray] = None       # (M,) coefficients of V in that basis
+    tcoef: Optional[np.ndarray] = None      # (steps, M): V(t_n) = sum_m tcoef[n, m] phi_m
 
     def __post_init__(self):
         if self.period is None:
@@ -182,6 +183,40 @@ def config3(n: int = 256, steps: int = 200, seed: int = 3) -> Workload:
     V = fourier_field([n, n, n], kv, amp, ph)
     return Workload("3d_torus_%d^3" % n, (n, n, n), 0.02, (0.2, -0.1, 0.05), steps,
                     np.zeros((n, n, n)), V)
+
+
+# ----------------------------------------------------------------------------
+# The paper's own experiments (Section 5): 1-D, period 2 pi, space step
+# h = pi / K (2K points), time step about sqrt(h), final time T = 8.
+# ----------------------------------------------------------------------------
+def paper_time_step(h: float, T: float = 8.0) -> Tuple[float, int]:
+    """A time step near sqrt(h) (the experiments' choice) that divides T, so
+    runs on different grids end at the same time: tau = T / ceil(T / sqrt(h))."""
+    steps = int(math.ceil(T / math.sqrt(h)))
+    return T / steps, steps
+
+
+def pendulum(K: int, T: float = 8.0) -> Workload:
+    """Section 5.1: P = 0, V = 1 - cos x, u0 = cos x on the 2 pi torus with
+    h = pi / K (2K grid points) and tau ~ sqrt(h), run to T."""
+    n = 2 * K
+    tau, steps = paper_time_step(math.pi / K, T)
+    cosx = fourier_field([n], np.array([[1]]), np.ones(1), np.zeros(1))
+    return Workload("pendulum_%d" % n, (n,), tau, (0.0,), steps, cosx.copy(), 1.0 - cosx,
+                    period=(TWO_PI,))
+
+
+def time_dependent(K: int, T: float = 8.0) -> Workload:
+    """Section 5.2: P = 1, V(t, x) = cos 2x sin t, u0 = cos x, same grids and
+    time steps as the pendulum.  V is given as one basis table (cos 2x) with
+    the coefficient sin(t_n) at step n, t_n = n tau."""
+    n = 2 * K
+    tau, steps = paper_time_step(math.pi / K, T)
+    cosx = fourier_field([n], np.array([[1]]), np.ones(1), np.zeros(1))
+    basis = fourier_field([n], np.array([[2]]), np.ones(1), np.zeros(1))[None]
+    tcoef = np.sin(tau * np.arange(steps, dtype=np.float64))[:, None]
+    return Workload("time_dependent_%d" % n, (n,), tau, (1.0,), steps, cosx, None,
+                    period=(TWO_PI,), basis=basis, tcoef=tcoef)
 
 
 @dataclasses.dataclass

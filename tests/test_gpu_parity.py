@@ -288,7 +288,7 @@ def test_config3_full_size_first_steps(torch_dev, orc, method):
 
 
 @pytest.mark.parametrize("n,tau,P", [((64,), 0.05, (0.3,)), ((256,), 0.02, (-0.4,)), ((48, 40), 0.04, (0.2, -0.1)),
-                                     ((72, 33), 0.03, (0.1, 0.5))])
+                                     ((72, 33), 0.03, (0.1, 0.5)), ((4096,), 0.02, (0.3,)), ((1000, 9), 0.03, (0.2, 0.1))])
 def test_fast_argmins_attain_the_value(torch_dev, orc, n, tau, P):
     """Fast-path argmins (in-place row sweeps included): every offset
     reproduces the returned value exactly from the plan's cost table, and
