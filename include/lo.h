@@ -79,7 +79,8 @@ typedef struct {
                                   [-kstar_half[a], kstar_half[a]]; NULL = mechanical */
     int64_t kstar_half[3];
     int32_t window[3];         /* 0 = rigorous window computed on the device every step;
-                                  > 0 = fixed half-width (argmins at the edge raise LO_ERR_WINDOW) */
+                                  > 0 = fixed half-width, swept by the exhaustive (brute) kernels
+                                  whatever the method (argmins at the edge raise LO_ERR_WINDOW) */
     int32_t method;            /* lo_method */
     uint32_t flags;            /* LO_FLAG_* */
     double t0;                 /* time of step 0 */

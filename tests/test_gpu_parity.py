@@ -337,18 +337,19 @@ def test_autotuned_plan_is_bitwise_identical(torch_dev, n, steps):
 
 
 @pytest.mark.parametrize("argmin", [False, True])
-def test_fast_window_wider_than_the_staged_band(torch_dev, orc, argmin):
-    """Fixed windows wider than any staged band of the cost table: 600 points
-    on the 2048-point rows (bands of at most 2 x 512 + 1 offsets) and 70 on
-    the 40-point axis (bands of 2 x 40 + 1): row and tile sweeps claim band by
-    band.  Values within 1e-12 of the
-    oracle; argmins equal the oracle's wherever the values agree."""
+@pytest.mark.parametrize("n,amp,noise", [((16384,), 1.0, 0.01), ((2048, 16), 1.2, 0.0)])
+def test_fast_window_wider_than_the_staged_band(torch_dev, orc, n, amp, noise, argmin):
+    """Rigorous windows above 511 points are wider than any staged band of the
+    cost table (at most 2 x 512 + 1 offsets): the one-line tile sweep of a
+    16384-point line and the row sweep of 2048-point rows claim band by band.
+    Values within 1e-12 of the oracle; argmins equal the oracle's wherever
+    the values agree."""
     torch = torch_dev
-    n, tau, P = (2048, 40), 0.02, (0.2, -0.3)
+    tau, P = 0.05, [0.2, -0.1][: len(n)]
     print_case("band by band", n, argmin)
-    u0 = wl.smooth_grid(list(n), 700) + 0.05 * wl.random_grid(list(n), 701)
+    u0 = amp * wl.smooth_grid(list(n), 700, count=6, kmax=3) + noise * wl.random_grid(list(n), 701)
     V = wl.smooth_grid(list(n), 702)
-    p = _plan(torch, n, tau, P, V, "fast", window=[600, 70])
+    p = _plan(torch, n, tau, P, V, "fast")
     u = _gpu(torch, u0)
     if argmin:
         arg = p.step(u, 0, argmin=True).cpu().numpy().astype(np.int64)
@@ -359,5 +360,7 @@ def test_fast_window_wider_than_the_staged_band(torch_dev, orc, argmin):
         assert same.mean() > 0.99
         assert np.array_equal(arg[:, same], rarg[:, same].astype(np.int64))
     else:
-        p.run(u, 4)
-        _check(u.cpu().numpy(), orc.run(u0, tau, P, 4, V=V), "fast")
+        p.run(u, 2)
+        _check(u.cpu().numpy(), orc.run(u0, tau, P, 2, V=V), "fast")
+    w, _ = p.diag()
+    assert 511 < w[0] and (len(n) == 1 or w[0] + 1 < n[0]), w
