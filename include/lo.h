@@ -59,7 +59,10 @@ typedef enum {
 
 typedef enum {
     LO_BRUTE = 0,   /* windowed exhaustive minimum: bit-exact with the definition */
-    LO_FAST = 1     /* lower-envelope kernel, O(1) per point; mechanical cost only */
+    LO_FAST = 1     /* claim (lower-envelope) kernels: each source claims the targets where it
+                       beats its neighbours.  O(1) per point for the mechanical cost, the
+                       minimum within 1e-12; O(log window) per point for a caller's convex
+                       table (crossings by bisection), the minimum and argmins exact */
 } lo_method;
 
 /* flags */

@@ -323,7 +323,7 @@ void choose_kernels(lo_plan_t p)
     const bool fast = p->d.method == LO_FAST;
     for (int a = 0; a < p->ndim; a++) {
         const int64_t N = p->n[a];
-        p->fast[a] = fast && !p->user_table[a];
+        p->fast[a] = fast;
         // fast: whole rows of a multiple of 8 points for axis 0, tiles otherwise
         const bool row_ok = a == 0 && N <= 2048 &&
                             (p->fast[a] ? N % 8 == 0 && fast_lds_for(kKindRow, N, 0, 1, 1) <= fbudget
@@ -567,6 +567,7 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.cq = p->dx[a] * p->dx[a] / (2.0 * p->d.tau);
         A.inv2c = 1.0 / (2.0 * A.cq);
         A.pofs = p->d.P[a] * p->d.tau / p->dx[a];
+        A.kslack = 0x1p-40 * (1.0 + p->kmaxabs[a]);
         if (a == 0) {
             // windows of step n + 1 from the statistics of u^n (slot n), one step early
             A.winp_dev = p->dwinp;

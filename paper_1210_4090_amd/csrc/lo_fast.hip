@@ -101,27 +101,64 @@ __host__ __device__ inline size_t claim_lds_bytes(const ClaimLds& f)
 
 namespace {
 
+// Largest s in [sl, sh] with K[s] - K[s - 1] <= D, or sl - 1 if there is none
+// (K covers [sl - 1, sh]; its differences are nondecreasing: a convex cost).
+__device__ __forceinline__ int table_cross(const double* K, int sl, int sh, double D)
+{
+    int lo = sl - 1, hi = sh;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (K[mid] - K[mid - 1] <= D)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // Claims of one chunk: sources p0 .. min(p0 + kCh - 1, plast) (lifted) of one
 // line with uu[k] = u(p0 - 1 + k), k = 0 .. kCh + 1.  Targets are clipped to
-// [tmin, tmax] (lifted) and to t - p in [smin, smax], a range the centred cost
-// table K (LDS or global; K[s] = k(s)) covers; key(t) gives the LDS slot of
-// lifted target t.  PASS 0: atomic minimum of the candidate into W; PASS 1:
-// among the candidates equal to W, atomic minimum of the offset
-// (source - target) into A.
-template <int PASS, int CH, typename KeyOf>
+// [tmin, tmax] (lifted) and to t - p in [smin, smax], a range the staged cost
+// table K (K[s] = k(s), in LDS) covers; key(t) gives the LDS slot of lifted
+// target t.  PASS 0: atomic minimum of the candidate into W; PASS 1: among
+// the candidates equal to W, atomic minimum of the offset (source - target)
+// into A.
+//
+// Crossings.  Mechanical cost (GEN false): the parabolas of sources j and
+// j + 1 cross at sigma = j + 1/2 + (u(j+1) - u(j)) / (2c) + P tau / dx, widened
+// by kEps cells.  Any convex table (GEN true; K must also cover smin - 1):
+// source j is no worse than j + 1 at offset s exactly when
+// k(s) - k(s - 1) <= u(j+1) - u(j), a monotone condition found by bisection
+// over the staged differences, with the comparison widened by
+// gsl + 2^-40 (|u(j)| + |u(j+1)|), far above the rounding of the candidates,
+// so that every minimiser (ties included) stays among the claimants.
+template <int PASS, int CH, bool GEN, typename KeyOf>
 __device__ __forceinline__ void claim_chunk(const double (&uu)[CH + 2], int p0, int plast, int tmin, int tmax,
                                             int smin, int smax, const double* K, double inv2c, double pofs,
-                                            double* W, int* A, KeyOf key)
+                                            double gsl, double* W, int* A, KeyOf key)
 {
     // crossing k lies between sources p0 - 1 + k and p0 + k
     int lo[CH + 1], hi[CH + 1];
-    double jh = (double)p0 - 0.5;
+    if (GEN) {
 #pragma unroll
-    for (int k = 0; k <= CH; k++) {
-        const double sg = jh + ((uu[k + 1] - uu[k]) * inv2c + pofs);
-        lo[k] = (int)floor(sg - kEps);   // source p0 + k claims from lo[k] + 1
-        hi[k] = (int)floor(sg + kEps);   // source p0 - 1 + k claims up to hi[k]
-        jh += 1.0;
+        for (int k = 0; k <= CH; k++) {
+            const int j = p0 - 1 + k;
+            const double D = uu[k + 1] - uu[k];
+            const double dl = gsl + 0x1p-40 * (fabs(uu[k]) + fabs(uu[k + 1]));
+            const int sp = table_cross(K, smin, smax, D + dl);
+            const int sm = (sp >= smin && K[sp] - K[sp - 1] > D - dl) ? table_cross(K, smin, sp, D - dl) : sp;
+            lo[k] = j + sm;   // source p0 + k claims from lo[k] + 1
+            hi[k] = j + sp;   // source p0 - 1 + k claims up to hi[k]
+        }
+    } else {
+        double jh = (double)p0 - 0.5;
+#pragma unroll
+        for (int k = 0; k <= CH; k++) {
+            const double sg = jh + ((uu[k + 1] - uu[k]) * inv2c + pofs);
+            lo[k] = (int)floor(sg - kEps);   // source p0 + k claims from lo[k] + 1
+            hi[k] = (int)floor(sg + kEps);   // source p0 - 1 + k claims up to hi[k]
+            jh += 1.0;
+        }
     }
 #pragma unroll
     for (int k = 0; k < CH; k++) {
@@ -185,8 +222,8 @@ __device__ __forceinline__ void publish_stats(SweepStats& st, const SweepArgs& a
 // The plain sweep (no epilogue, no argmins) is held to 128 registers (it fits
 // without spilling): four waves a SIMD.
 // ---------------------------------------------------------------------------
-template <int EPI, int ARG, int CH, int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(CH == 8 && !ARG && !EPI ? 4 : 1))) void
+template <int EPI, int ARG, int CH, int BS, bool GEN>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(CH == 8 && !ARG && !EPI && !GEN ? 4 : 1))) void
 k_claim_row(const double* __restrict__ in, double* __restrict__ out, const double* __restrict__ kc, SweepArgs a,
             ClaimLds L, double inv2c, double pofs)
 {
@@ -221,16 +258,19 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
     // never win)
     const int kcap = (int)min((int64_t)a.kin.kcap, (int64_t)0x7fffffff);
     const int smin = max(-wm - 1, -kcap), smax = min(wp + 1, kcap);
-    // KT[i] = k(smin + i), i < 2 KH + 1: the window's band
+    // KT[i] = k(sb + i), i < 2 KH + 1: the window's band (a convex table's
+    // crossings also read k(smin - 1))
+    const int g = GEN ? 1 : 0, sb = smin - g;
     for (int i = threadIdx.x; i < 2 * KH + 1; i += BS) {
-        const int s = smin + i;
+        const int s = sb + i;
         KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
     }
     // claims wrap once around the row (targets t of sources 0 .. N - 1 lie in
     // [smin, N - 1 + smax]); the main path needs the window inside the band
     const bool wraps = wp + 1 < N && wm + 1 < N;
-    const bool fast = wraps && smax - smin <= 2 * KH;
-    const double* K = KT - smin;   // K[s] = k(s), s in [smin, smax]
+    const bool fast = wraps && smax - sb <= 2 * KH;
+    const double* K = KT - sb;   // K[s] = k(s), s in [sb, smax]
+    const double gsl = a.kslack;
     const int kbase = r * N;
     auto key = [N, kbase](int t) { return skc<CH>(kbase + (t < 0 ? t + N : (t >= N ? t - N : t))); };
 
@@ -291,11 +331,11 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
                 }
             }
             for (int pass = 0; pass < (ARG ? 2 : 1); pass++) {
-                for (int blo = smin; blo <= smax; blo += 2 * KH + 1) {
-                    const int bhi = min(blo + 2 * KH, smax);
+                for (int blo = smin; blo <= smax; blo += max(2 * KH + 1 - g, 1)) {
+                    const int bhi = min(blo + max(2 * KH - g, 0), smax);
                     __syncthreads();
                     for (int i = threadIdx.x; i < 2 * KH + 1; i += BS) {
-                        const int s = blo + i;
+                        const int s = blo - g + i;
                         KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
                     }
                     __syncthreads();
@@ -311,11 +351,11 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
                                 j = j + 1 == N ? 0 : j + 1;
                             }
                             if (pass == 0)
-                                claim_chunk<0, 2>(u4, p0 + k, N - 1, smin, N - 1 + smax, blo, bhi, KT - blo, inv2c,
-                                                  pofs, W, A, key);
+                                claim_chunk<0, 2, GEN>(u4, p0 + k, N - 1, smin, N - 1 + smax, blo, bhi,
+                                                       KT - (blo - g), inv2c, pofs, gsl, W, A, key);
                             else
-                                claim_chunk<1, 2>(u4, p0 + k, N - 1, smin, N - 1 + smax, blo, bhi, KT - blo, inv2c,
-                                                  pofs, W, A, key);
+                                claim_chunk<1, 2, GEN>(u4, p0 + k, N - 1, smin, N - 1 + smax, blo, bhi,
+                                                       KT - (blo - g), inv2c, pofs, gsl, W, A, key);
                         }
                     }
                 }
@@ -348,10 +388,14 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
             }
             __syncthreads();
             if (fast) {
-                if (ok) claim_chunk<0, CH>(uu, p0, N - 1, smin, N - 1 + smax, smin, smax, K, inv2c, pofs, W, A, key);
+                if (ok)
+                    claim_chunk<0, CH, GEN>(uu, p0, N - 1, smin, N - 1 + smax, smin, smax, K, inv2c, pofs, gsl, W, A,
+                                            key);
                 __syncthreads();
                 if (ARG) {
-                    if (ok) claim_chunk<1, CH>(uu, p0, N - 1, smin, N - 1 + smax, smin, smax, K, inv2c, pofs, W, A, key);
+                    if (ok)
+                        claim_chunk<1, CH, GEN>(uu, p0, N - 1, smin, N - 1 + smax, smin, smax, K, inv2c, pofs, gsl,
+                                                W, A, key);
                     __syncthreads();
                 }
             } else {
@@ -430,7 +474,7 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
 // then the whole block works on one line) x R targets [r0, r0 + R) (+ target
 // r0 + R for the forward differences of the output), lines of any stride.
 // ---------------------------------------------------------------------------
-template <int EPI, int ARG, int C>
+template <int EPI, int ARG, int C, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict__ in, double* __restrict__ out,
                                                        const double* __restrict__ kc, SweepArgs a, ClaimLds L,
                                                        double inv2c, double pofs)
@@ -479,13 +523,16 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
     // offsets beyond the table's end cost +inf and never win
     const int kcap = (int)min((int64_t)a.kin.kcap, (int64_t)0x7fffffff);
     const int smin = max(-wm - 1, -kcap), smax = min(wp + 1, kcap);
-    // KT[i] = k(smin + i), i < 2 KH + 1: the window's band
+    // KT[i] = k(sb + i), i < 2 KH + 1: the window's band (a convex table's
+    // crossings also read k(smin - 1))
+    const int g = GEN ? 1 : 0, sb = smin - g;
     for (int i = threadIdx.x; i < 2 * KH + 1; i += kBlock) {
-        const int s = smin + i;
+        const int s = sb + i;
         KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
     }
-    const bool fast = smax - smin <= 2 * KH;
-    const double* K = KT - smin;   // K[s] = k(s), s in [smin, smax]
+    const bool fast = smax - sb <= 2 * KH;
+    const double* K = KT - sb;   // K[s] = k(s), s in [sb, smax]
+    const double gsl = a.kslack;
     for (int t = q; t < NT; t += kBlock / C) {
         W[t * kKeyStride + c] = INFINITY;
         if (ARG) A[t * kKeyStride + c] = 0x7fffffff;
@@ -510,20 +557,22 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
                 }
                 auto key = [r0](int t) { return (t - r0) * kKeyStride; };
                 if (pass == 0)
-                    claim_chunk<0, kCh>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, W + c, A + c, key);
+                    claim_chunk<0, kCh, GEN>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, gsl, W + c,
+                                             A + c, key);
                 else
-                    claim_chunk<1, kCh>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, W + c, A + c, key);
+                    claim_chunk<1, kCh, GEN>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, gsl, W + c,
+                                             A + c, key);
             }
             __syncthreads();
         }
     } else {
         // window wider than the band: band by band, chunks of two sources
         for (int pass = 0; pass < (ARG ? 2 : 1); pass++) {
-            for (int blo = smin; blo <= smax; blo += 2 * KH + 1) {
-                const int bhi = min(blo + 2 * KH, smax);
+            for (int blo = smin; blo <= smax; blo += max(2 * KH + 1 - g, 1)) {
+                const int bhi = min(blo + max(2 * KH - g, 0), smax);
                 __syncthreads();
                 for (int i = threadIdx.x; i < 2 * KH + 1; i += kBlock) {
-                    const int s = blo + i;
+                    const int s = blo - g + i;
                     KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
                 }
                 __syncthreads();
@@ -542,11 +591,11 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
                     }
                     auto key = [r0](int t) { return (t - r0) * kKeyStride; };
                     if (pass == 0)
-                        claim_chunk<0, 2>(u4, p0, pB, r0, r0 + NT - 1, blo, bhi, KT - blo, inv2c, pofs, W + c, A + c,
-                                          key);
+                        claim_chunk<0, 2, GEN>(u4, p0, pB, r0, r0 + NT - 1, blo, bhi, KT - (blo - g), inv2c, pofs,
+                                               gsl, W + c, A + c, key);
                     else
-                        claim_chunk<1, 2>(u4, p0, pB, r0, r0 + NT - 1, blo, bhi, KT - blo, inv2c, pofs, W + c, A + c,
-                                          key);
+                        claim_chunk<1, 2, GEN>(u4, p0, pB, r0, r0 + NT - 1, blo, bhi, KT - (blo - g), inv2c, pofs,
+                                               gsl, W + c, A + c, key);
                 }
             }
             __syncthreads();
@@ -614,18 +663,28 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
     const size_t lds = claim_lds_bytes(L);
     const bool arg = a.argmin != nullptr;
     const bool epi = a.hv != nullptr;
-#define LO_CLAIM_LAUNCH(K, E, A)                                                                              \
+#define LO_CLAIM_LAUNCH_G(K, E, A, G)                                                                          \
     do {                                                                                                        \
         if (L.C == 1)                                                                                           \
-            hipLaunchKernelGGL((K<E, A, 1>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out, a.kin.k, \
-                               a, L, inv2c, pofs);                                                              \
-        else                                                                                                    \
-            hipLaunchKernelGGL((K<E, A, kTileLines>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out, \
+            hipLaunchKernelGGL((K<E, A, 1, G>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out,       \
                                a.kin.k, a, L, inv2c, pofs);                                                     \
+        else                                                                                                    \
+            hipLaunchKernelGGL((K<E, A, kTileLines, G>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in,   \
+                               out, a.kin.k, a, L, inv2c, pofs);                                                \
     } while (0)
-#define LO_ROW_LAUNCH_CH(E, A, CH)                                                                            \
-    hipLaunchKernelGGL((k_claim_row<E, A, CH, kRowPoints / CH>), dim3((unsigned)grid, a.nb),                  \
+#define LO_CLAIM_LAUNCH(K, E, A)                                                                                \
+    do {                                                                                                        \
+        if (a.quad) LO_CLAIM_LAUNCH_G(K, E, A, false);                                                          \
+        else LO_CLAIM_LAUNCH_G(K, E, A, true);                                                                  \
+    } while (0)
+#define LO_ROW_LAUNCH_G(E, A, CH, G)                                                                          \
+    hipLaunchKernelGGL((k_claim_row<E, A, CH, kRowPoints / CH, G>), dim3((unsigned)grid, a.nb),               \
                        dim3(kRowPoints / CH), lds, s, in, out, a.kin.k, a, L, inv2c, pofs)
+#define LO_ROW_LAUNCH_CH(E, A, CH)                                                                            \
+    do {                                                                                                       \
+        if (a.quad) LO_ROW_LAUNCH_G(E, A, CH, false);                                                          \
+        else LO_ROW_LAUNCH_G(E, A, CH, true);                                                                  \
+    } while (0)
 #define LO_ROW_LAUNCH(E, A)                                                                                    \
     do {                                                                                                       \
         if (a.row_ch == 4) LO_ROW_LAUNCH_CH(E, A, 4);                                                          \
@@ -649,8 +708,10 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
         }
     }
 #undef LO_CLAIM_LAUNCH
+#undef LO_CLAIM_LAUNCH_G
 #undef LO_ROW_LAUNCH
 #undef LO_ROW_LAUNCH_CH
+#undef LO_ROW_LAUNCH_G
     return hipGetLastError();
 }
 

@@ -92,11 +92,12 @@ struct SweepArgs {
     int tile_rows;              // targets per tile (tile kernels)
     int kind;                   // kKindRow or kKindTile
     int cap_is_error;           // 0 when the kinetic table is the cost's whole support
-    int fast;                   // claim kernel (mechanical cost only)
+    int fast;                   // claim kernel (any convex cost)
     int quad;                   // the cost is the mechanical c s^2 - p s (window guesses)
     double cq;                  // c = dx^2 / (2 tau): k(s) = c s^2 - p s
     double inv2c;               // 1 / (2c)
     double pofs;                // p / (2c) = P tau / dx
+    double kslack;              // 2^-40 (1 + max |k|): rounding slack of a table's crossings
     const int* win_in;          // this step's windows: [2a] = W+, [2a+1] = W- of axis a
     // batched launches: blockIdx.y is the instance; its arrays, kinetic
     // table, stats slots and windows sit at these strides from instance 0's

@@ -189,22 +189,56 @@ def test_static_basis_potential(torch_dev, orc):
     assert np.array_equal(u.cpu().numpy(), ref)
 
 
-def test_user_convex_kinetic_table(torch_dev, orc):
-    """A general convex tau*K* (hypothesis (i)) given as a table."""
+def _quartic_table(N, tau, half, P=0.2, q=0.1):
+    """tau K*(s dx / tau) for K*(v) = v^2/2 + q v^4 - P v, s in [-half, half]
+    (convex: hypothesis (i)); an input, evaluated the same way for both sides."""
+    d = np.arange(-half, half + 1) / N
+    return tau * (0.5 * (d / tau) ** 2 + q * (d / tau) ** 4) - P * d
+
+
+@pytest.mark.parametrize("method", ["brute", "fast"])
+def test_user_convex_kinetic_table(torch_dev, orc, method):
+    """A general convex tau*K* (hypothesis (i)) given as a table: both
+    methods equal the oracle bit for bit."""
     torch = torch_dev
     N, tau = 90, 0.05
-    s = np.arange(-60, 61)
-    d = s / N
-    tab = tau * (0.5 * (d / tau) ** 2 + 0.1 * (d / tau) ** 4) - 0.2 * d
+    tab = _quartic_table(N, tau, 60)
     u0 = wl.smooth_grid([N], 71) + 0.1 * wl.random_grid([N], 72)
     V = wl.smooth_grid([N], 73)
     ref = u0.copy()
     for k in range(6):
         ref = orc.step(ref, tau, [0.0], V, ktabs=[tab])
-    p = _plan(torch, [N], tau, [0.0], V, kstar_tabs=[tab])
+    p = _plan(torch, [N], tau, [0.0], V, method=method, kstar_tabs=[tab])
     u = _gpu(torch, u0)
     p.run(u, 6)
     assert np.array_equal(u.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("n,tau,half", [((96, 72), 0.04, (150, 120)), ((16384,), 0.05, (16000,))])
+def test_fast_convex_table_values_and_argmins_exact(torch_dev, orc, n, tau, half):
+    """Claims whose crossings come from bisection over a caller's convex
+    table: one step with argmins, then a short run, equal to the oracle bit
+    for bit (values and argmins).  On the 16384-point line the windows exceed
+    every staged band, so the band-by-band path runs as well."""
+    torch = torch_dev
+    print_case("convex table fast", n)
+    tabs = [_quartic_table(n[a], tau, half[a], P=[0.2, -0.3][a]) for a in range(len(n))]
+    u0 = wl.smooth_grid(list(n), 800) + 0.05 * wl.random_grid(list(n), 801)
+    V = wl.smooth_grid(list(n), 802)
+    P0 = [0.0] * len(n)
+    p = _plan(torch, n, tau, P0, V, "fast", kstar_tabs=tabs)
+    u = _gpu(torch, u0)
+    arg = p.step(u, 0, argmin=True).cpu().numpy().astype(np.int64)
+    ref, rarg = orc.step(u0, tau, P0, V=V, ktabs=tabs, with_argmin=True)
+    assert np.array_equal(u.cpu().numpy(), ref)
+    assert np.array_equal(arg, rarg.astype(np.int64))
+    p.run(u, 3, n0=1)
+    for k in range(3):
+        ref = orc.step(ref, tau, P0, V=V, ktabs=tabs)
+    assert np.array_equal(u.cpu().numpy(), ref)
+    if len(n) == 1:
+        w, _ = p.diag()
+        assert w[0] > 511, w
 
 
 def test_fixed_window_saturation_is_reported(torch_dev):
