@@ -209,6 +209,42 @@ def measure_paper_pendulum(torch, method, K=2 ** 17, reps=None):
             "paper_setting": "MATLAB, 2.3 GHz Intel Core i7 laptop, approximate decomposition eta = h"}
 
 
+def measure_decomposition(torch, K=2 ** 13, etas=(0.0, 0.01, 1.0)):
+    """The paper's own algorithm (Section 4; lo_run_decomp) on the pendulum
+    with 2K points to T = 8, for tolerances eta (on slope increments; eta = 1
+    is the paper's eta = h on raw increments), against the exact claim path:
+    device time, pieces and convex/concave breaks per step, relative error."""
+    import numpy as np
+    from paper_1210_4090_amd import workloads as wl
+    from paper_1210_4090_amd.lo import Plan
+    w = wl.pendulum(K)
+    p = Plan(w.n, w.tau, w.P, period=w.period, V=torch.as_tensor(w.V, device="cuda"), method="fast")
+    u0 = torch.as_tensor(w.u0, device="cuda")
+
+    def timed(fn):
+        u = u0.clone()
+        fn(u, 2)                  # warm-up
+        u = u0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn(u, w.steps)
+        torch.cuda.synchronize()
+        return u, time.perf_counter() - t0, r
+
+    exact, tc, _ = timed(lambda u, k: p.run(u, k))
+    window = p.diag()[0][0] + 2
+    ex = exact.cpu().numpy()
+    runs = []
+    for eta in etas:
+        u, dt, (pieces, breaks) = timed(lambda u, k, e=eta: p.run_decomp(u, k, eta=e, window=window))
+        runs.append({"eta": eta, "ms_per_run": dt * 1e3, "pieces_per_step": pieces / w.steps,
+                     "breaks_per_step": breaks / w.steps,
+                     "max_rel_err_vs_exact": float(np.max(np.abs(u.cpu().numpy() - ex)) / np.max(np.abs(ex)))})
+    p.close()
+    return {"grid_points": w.npts, "steps": w.steps, "window": int(window), "claim_path_ms": tc * 1e3,
+            "decomposition": runs}
+
+
 def cpu_baseline(w, nsteps=30):
     from oracle import oracle
     t0 = time.perf_counter()
@@ -289,6 +325,8 @@ def main():
         extras["fwd_adjoint_1024^2_500steps"] = measure_adjoint(torch, args.method)
         extras["paper_pendulum_2^18"] = measure_paper_pendulum(torch, args.method)
         log("paper pendulum: %s" % extras["paper_pendulum_2^18"])
+        extras["paper_decomposition_pendulum_2^14"] = measure_decomposition(torch)
+        log("paper decomposition: %s" % extras["paper_decomposition_pendulum_2^14"])
         if args.method == "fast":
             mt = measure_workload(torch, w, "fast", 2, 1, autotune=True)
             extras["headline_workload_autotuned"] = {"updates_per_s": mt["rate"], "ms_per_run": mt["ms_per_run"],

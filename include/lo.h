@@ -170,6 +170,26 @@ lo_status lo_kinetic_table(lo_plan_t plan, int32_t axis, int64_t s0, int64_t cou
  * same stream each step.  Synchronous. */
 lo_status lo_time_kernels(lo_plan_t plan, double* u, int64_t n0, int64_t nsteps, double* ms, void* stream);
 
+/* Comparison path: the paper's own fast algorithm (Section 4) on a 1-D plan.
+ * Each step splits the lifted line into convex and concave pieces (a convex
+ * piece continues while its slopes drop by at most eta, a concave one while
+ * they rise by at most eta: Section 4.3's tolerance; eta = 0 is exact),
+ * convolves each piece with the kinetic cost restricted to offsets
+ * [-window, window] in linear time (Theorem th:convex; Theorem th:ccc and
+ * Lemma lm:simplif for concave pieces), takes the minimum over the pieces and
+ * subtracts tau V(t_n).  Runs steps n0 .. n0+nsteps-1 on u (device [n[0]]).
+ * window = 0 takes the plan's whole cost table; a window that holds every
+ * minimiser with eta = 0 gives the definition's result (every value is a
+ * genuine candidate; near-ties may pick one a few ulps off).  pieces / breaks
+ * (host, may be NULL) receive the pieces convolved over the run and the
+ * breaks between pieces of different type (pieces also end at the borders of
+ * the 64-source segments that GPU threads take).  LO_ERR_UNSUPPORTED unless
+ * the plan is 1-D and not batched; LO_ERR_INVALID for eta < 0, window < 0 or
+ * above the plan's table, or steps beyond a time-dependent potential's
+ * schedule.  Synchronous; allocates its scratch in the plan on first use. */
+lo_status lo_run_decomp(lo_plan_t plan, double* u, int64_t n0, int64_t nsteps, double eta, int32_t window,
+                        int64_t* pieces, int64_t* breaks, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,6 +48,8 @@ struct lo_plan_s {
     double* dcoef = nullptr;     // [nmodes] static coefficients
     double* dtcoef = nullptr;    // [ntcoef][nmodes]
     double* dhv = nullptr;       // tau*V (static) or the current step's tau*V(t_n)
+    double* dc_w = nullptr;      // lo_run_decomp: sweep output [npts]
+    unsigned long long* dc_cnt = nullptr;   // lo_run_decomp: pieces, breaks
     bool has_v = false;
     bool time_dep = false;
     double dvf[kMaxDim] = {0, 0, 0}, dvb[kMaxDim] = {0, 0, 0};
@@ -164,6 +166,8 @@ void free_plan(lo_plan_t p)
     if (p->dpofs) (void)hipFree(p->dpofs);
     if (p->dwinp) (void)hipFree(p->dwinp);
     if (p->tune_u) (void)hipFree(p->tune_u);
+    if (p->dc_w) (void)hipFree(p->dc_w);
+    if (p->dc_cnt) (void)hipFree(p->dc_cnt);
     delete p;
 }
 
@@ -941,6 +945,37 @@ lo_status lo_run(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckp
         }
     }
     return finish(p, s, false);
+}
+
+lo_status lo_run_decomp(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, double eta, int32_t window,
+                        int64_t* pieces, int64_t* breaks, void* stream)
+{
+    if (!p || !u || nsteps < 0 || !(eta >= 0.0) || window < 0) return LO_ERR_INVALID;
+    if (p->ndim != 1 || p->nb != 1) return LO_ERR_UNSUPPORTED;
+    const int64_t N = p->n[0];
+    const int64_t W = window > 0 ? window : p->kcap[0];
+    if (W > p->kcap[0] || N + 2 * W > (int64_t)1 << 30) return LO_ERR_INVALID;
+    if (p->time_dep && n0 + nsteps > p->ntcoef) return LO_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->dc_w) {
+        lo_status st = alloc((void**)&p->dc_w, sizeof(double) * (size_t)N);
+        if (!st) st = alloc((void**)&p->dc_cnt, sizeof(unsigned long long) * 2);
+        if (st) return st;
+    }
+    HIPCHK(hipMemsetAsync(p->dc_cnt, 0, sizeof(unsigned long long) * 2, s));
+    for (int64_t k = 0; k < nsteps; k++) {
+        const int64_t n = n0 + k;
+        if (p->time_dep)
+            HIPCHK(launch_synth_hv(p->basis, p->dtcoef + n * p->nmodes, p->nmodes, p->npts, p->d.tau, p->dhv, s));
+        HIPCHK(launch_decomp_step(u, p->dc_w, u, (int)N, (int)W, p->dkt[0] + p->kcap[0], eta * p->dx[0],
+                                  p->has_v ? p->dhv : nullptr, p->dc_cnt, s));
+    }
+    unsigned long long c[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(c, p->dc_cnt, sizeof(c), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (pieces) *pieces = (int64_t)c[0];
+    if (breaks) *breaks = (int64_t)c[1];
+    return LO_OK;
 }
 
 lo_status lo_last_diag(lo_plan_t p, int32_t* window_used, int32_t* max_abs_offset)

@@ -131,6 +131,9 @@ hipError_t launch_diff_range(const double* u, const double* snap, int64_t npts, 
 hipError_t launch_synth_hv(const double* basis, const double* coef_dev, int nmodes, int64_t npts,
                            double tau, double* hv, hipStream_t s);
 hipError_t launch_scale(const double* V, double tau, int64_t npts, double* hv, hipStream_t s);
+// One step of the decomposition comparison path (1-D): u -> w (sweep) -> u_out = w - hv.
+hipError_t launch_decomp_step(const double* u, double* w, double* u_out, int N, int W, const double* kt_centre,
+                              double tol, const double* hv, unsigned long long* counts, hipStream_t s);
 hipError_t launch_potential_diffs(const double* V, int ndim, const int64_t* n, double* out6,
                                   hipStream_t s);
 hipError_t launch_sweep(int method, const double* in, double* out, const SweepArgs& a,

@@ -182,6 +182,19 @@ class Plan:
                                                        _stream(stream)))
         return ms[: self.ndim]
 
+    def run_decomp(self, u: torch.Tensor, nsteps: int, eta: float = 0.0, window: int = 0, n0: int = 0,
+                   stream=None):
+        """Comparison path (1-D plans): nsteps steps of the paper's convex /
+        concave decomposition algorithm with tolerance eta on offsets
+        [-window, window] (0: the plan's whole table).  Returns (pieces,
+        breaks) counted over the run."""
+        _dev_f64(u, "u", self.shape)
+        pieces, breaks = ctypes.c_int64(0), ctypes.c_int64(0)
+        check("lo_run_decomp", lib().lo_run_decomp(self._h, ctypes.c_void_p(u.data_ptr()), int(n0), int(nsteps),
+                                                   float(eta), int(window), ctypes.byref(pieces),
+                                                   ctypes.byref(breaks), _stream(stream)))
+        return pieces.value, breaks.value
+
     def kinetic_table(self, axis: int, s0: int, count: int) -> np.ndarray:
         out = np.empty(count, dtype=np.float64)
         check("lo_kinetic_table", lib().lo_kinetic_table(self._h, int(axis), int(s0), int(count),
