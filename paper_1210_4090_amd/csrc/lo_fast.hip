@@ -1,5 +1,6 @@
-// Fast axis sweep for the mechanical cost k(s) = c s^2 - p s
-// (c = dx^2 / (2 tau), p = P dx): O(1) work per point instead of O(window).
+// Fast axis sweep: O(1) work per point for the mechanical cost
+// k(s) = c s^2 - p s (c = dx^2 / (2 tau), p = P dx), O(log window) for any
+// convex cost table.
 //
 // For a target t the candidate cost of source j is F_t(j) = u_j + k(t - j).
 // Adjacent sources j, j+1 give equal costs at the real target
@@ -18,10 +19,12 @@
 // fl(u_j + k(t - j)) among its claimants (an LDS atomic minimum on doubles).
 // Sources that are not hull vertices only add genuine candidates (or claim
 // nothing, where sigma decreases), so the minimum is the minimum over all
-// sources -- no hull needs to be built.  (The paper's own fast convolution,
-// Section 4, splits u into convex and concave parts and merges slope
-// sequences; this claim form is what turns the same convexity into
-// independent per-source work for a wavefront.)
+// sources -- no hull needs to be built.  For a convex table the same holds
+// with the crossing found by bisection: j is no worse than j + 1 at offset s
+// exactly when k(s) - k(s-1) <= u_{j+1} - u_j, a condition monotone in s.
+// (The paper's own fast convolution, Section 4, splits u into convex and
+// concave parts and merges slope sequences; this claim form is what turns the
+// same convexity into independent per-source work for a wavefront.)
 //
 // A minimiser lies within the step's window, so claims are clipped to it; a
 // clipped candidate is never the minimum.  Costs come from a band of 2 KH + 1
@@ -29,23 +32,26 @@
 // starting at the window's low end, so an asymmetric window (a large |P|
 // shifts the minimisers) fits whenever its width does.  A wider window is
 // claimed band by band, restaging the table between bands (minima over the
-// union of the candidates are the same), in chunks of two sources so that this
-// rare path needs fewer registers than the main one.  The kept value is a genuine candidate of the
-// definition and equals the exhaustive minimum except where two candidates
-// differ by a few ulps.  Ties are broken by a second pass that keeps the
-// smallest offset (lowest lifted source) among the claimants attaining the
-// minimum.  Row sweeps whose window reaches a whole row fall back to the
-// exhaustive loop.
+// union of the candidates are the same), in chunks of two sources so that
+// this rare path needs fewer registers than the main one.  The kept value is
+// a genuine candidate of the definition and equals the exhaustive minimum
+// except where two candidates differ by a few ulps (never, for a table: its
+// comparisons are widened in value).  Ties are broken by a second pass that
+// keeps the smallest offset (lowest lifted source) among the claimants
+// attaining the minimum.  Row sweeps whose window reaches a whole row fall
+// back to the exhaustive loop.
 //
 // Work layout: a thread takes chunks of kCh consecutive sources of one line,
 // loads the kCh + 2 values around them once, and computes every crossing once.
-//  - ROW kernel (axis 0, N a multiple of 8): each thread owns 8 consecutive
-//    points of a row (16-byte loads and stores), keys in LDS in a skewed
-//    layout (x -> x + x/8, so chunk-strided lanes hit distinct banks); claims
-//    wrap around the row, so no halo is read; persistent blocks.
-//  - TILE kernel (strided axes): 16 lines side by side x R targets; sources
-//    come straight from global memory (16 adjacent lines = 128 contiguous
-//    bytes per source), only the keys live in LDS.
+//  - ROW kernel (axis 0, N a multiple of 8, N <= 2048): each thread owns 8
+//    (or 4) consecutive points of a row (16-byte loads and stores), keys in
+//    LDS in a skewed layout (x -> x + x/8, so chunk-strided lanes hit distinct
+//    banks); claims wrap around the row, so no halo is read; persistent
+//    blocks.
+//  - TILE kernel (other axes): 16 lines side by side x R targets (one line x
+//    4R targets for an axis with fewer than 16 lines); sources come straight
+//    from global memory (16 adjacent lines = 128 contiguous bytes per
+//    source), only the keys and the cost band live in LDS.
 #include "lo_internal.h"
 #include "lo_device.h"
 

@@ -93,7 +93,7 @@ struct SweepArgs {
     int kind;                   // kKindRow or kKindTile
     int cap_is_error;           // 0 when the kinetic table is the cost's whole support
     int fast;                   // claim kernel (any convex cost)
-    int quad;                   // the cost is the mechanical c s^2 - p s (window guesses)
+    int quad;                   // the cost is the mechanical c s^2 - p s (window guesses, closed-form claim crossings)
     double cq;                  // c = dx^2 / (2 tau): k(s) = c s^2 - p s
     double inv2c;               // 1 / (2c)
     double pofs;                // p / (2c) = P tau / dx
