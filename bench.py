@@ -172,9 +172,14 @@ def measure_hbar(torch, method, subset=32):
         p.close()
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
+    # algorithmic bytes of every step of every instance: two sweeps of 16 B a
+    # point and the tau V table (8 B a point), over the whole job's time
+    step_bytes = float(sum(sweep_bytes(2, 1)))
     return {"instances": bw.ninst, "steps": steps, "total_points": float(pts.sum()),
             "batched_s": t_all, "hbar_per_s": bw.ninst / t_all,
             "updates_per_s": float(pts.sum()) * steps / t_all,
+            "effective_GBs_whole_job": float(pts.sum()) * steps * step_bytes / t_all / 1e9,
+            "hbm_frac_whole_job": float(pts.sum()) * steps * step_bytes / t_all / 1e9 / HBM_PEAK_GBS,
             "subset": int(subset), "subset_batched_s": t_sub, "subset_one_plan_each_s": t_loop,
             "subset_speedup_batched": t_loop / t_sub}
 
