@@ -175,6 +175,63 @@ int orc_sweep(int ndim, const int64_t* n, int axis, double dx, double tau, doubl
     return 0;
 }
 
+/*
+ * One step of the first discrete semigroup (Section 2.2, eq. cost1) on a 1-D
+ * periodic grid of N points with a static potential: the cost of moving from
+ * lifted source y to target x in one step is the action of the straight path
+ * between them, tau K*((x - y) dx / tau) minus the time integral of V along
+ * the path.  The integral is taken by the trapezoid rule over the grid points
+ * the path crosses, each crossed after tau / m of time (m = |x - y|), on the
+ * table hv = fl(tau V):
+ *     I(y, x) = hv[x]                                                m = 0,
+ *     I(y, x) = (hv[y]/2 + hv[y+d] + ... + hv[x-d] + hv[x]/2) / m      m > 0,
+ * d = sign(x - y), summed in path order from y.  Then
+ *     w[x] = min over lifted y of fl( fl(u[y] + k(x - y)) - I(y, x) ),
+ * with argmin the lowest lifted source (smallest e = y - x).  A source whose
+ * kinetic cost exceeds k(0) + osc(u) + osc(hv) cannot beat staying put, so
+ * that interval is enumerated.  hv may be NULL (V = 0).
+ */
+int orc_semigroup1_step(int64_t N, double dx, double tau, double P, const double* ktab, int64_t khalf,
+                        const double* hv, const double* u, double* w, int32_t* argmin)
+{
+    if (N < 1 || !(tau > 0)) return -1;
+    orc_kin K = {dx, tau, P, ktab, khalf};
+    double osc, umax, hosc = 0.0, hmax = 0.0;
+    array_stats(u, N, &osc, &umax);
+    if (hv) array_stats(hv, N, &hosc, &hmax);
+    int64_t slo, shi;
+    if (kin_interval(&K, osc + hosc, umax + hmax, &slo, &shi) != 0) return -2;
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < N; x++) {
+        double best = INFINITY;
+        int64_t arg = 0;
+        for (int64_t e = -shi; e <= -slo; e++) {
+            const int64_t y = x + e;   /* lifted source */
+            int ok;
+            const double k = kin_eval(&K, -e, &ok);
+            if (!ok) continue;
+            double I = 0.0;
+            if (hv) {
+                const int64_t m = e < 0 ? -e : e;
+                if (m == 0) {
+                    I = hv[x];
+                } else {
+                    const int64_t d = y < x ? 1 : -1;
+                    double sum = 0.5 * hv[imod(y, N)];
+                    for (int64_t i = 1; i < m; i++) sum = sum + hv[imod(y + i * d, N)];
+                    sum = sum + 0.5 * hv[x];
+                    I = sum / (double)m;
+                }
+            }
+            const double v = (u[imod(y, N)] + k) - I;
+            if (v < best) { best = v; arg = e; }
+        }
+        w[x] = best;
+        if (argmin) argmin[x] = (int32_t)arg;
+    }
+    return 0;
+}
+
 /* Potential synthesis  V[x] = sum_m fl(c_m * phi_m[x]), summed in m order. */
 int orc_potential(int64_t npts, int nmodes, const double* basis, const double* coef, double* V)
 {

@@ -5,7 +5,8 @@ CPU-baseline leg may import this module; the product package never does.
 
 Every function follows the plain definition of the fully discrete
 Lax--Oleinik scheme (Section 2.3, eq. eqconvol; Remark rk28 for the axis
-splitting; eq. uN for the composition); see lo_oracle.c for the exact
+splitting; eq. uN for the composition), or, for semigroup1_*, of the first
+discrete semigroup (Section 2.2, eq. cost1); see lo_oracle.c for the exact
 floating-point evaluation order.
 """
 from __future__ import annotations
@@ -56,8 +57,10 @@ def lib():
         L.orc_adjoint.argtypes = [ctypes.c_int, _i64p, _f64p, ctypes.c_double, _f64p, ctypes.c_int64,
                                   _f64p, ctypes.c_int, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
         L.orc_num_threads.argtypes = []
+        L.orc_semigroup1_step.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          _f64p, ctypes.c_int64, _f64p, _f64p, _f64p, _i32p]
         for f in ("orc_sweep", "orc_step", "orc_run", "orc_joint_step", "orc_potential",
-                  "orc_adjoint", "orc_num_threads"):
+                  "orc_adjoint", "orc_num_threads", "orc_semigroup1_step"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -210,3 +213,32 @@ def adjoint(u0: np.ndarray, tau: float, P: Sequence[float], nsteps: int, basis: 
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def semigroup1_step(u: np.ndarray, tau: float, P: float, V: Optional[np.ndarray] = None, period: float = 1.0,
+                    ktab: Optional[np.ndarray] = None, with_argmin: bool = False):
+    """One step of the first discrete semigroup (Section 2.2, eq. cost1) on a
+    1-D periodic grid with static V: the straight-path action, the time
+    integral of V by the trapezoid rule over the crossed grid points of
+    hv = fl(tau V) (lo_oracle.c).  Returns u+ (and int32 argmin offsets)."""
+    u = _c(u)
+    N = u.shape[0]
+    hv = None if V is None else _c(tau * _c(V))
+    kt = None if ktab is None else _c(ktab)
+    half = 0 if kt is None else (kt.shape[0] - 1) // 2
+    w = np.empty_like(u)
+    arg = np.empty(N, dtype=np.int32) if with_argmin else None
+    rc = lib().orc_semigroup1_step(N, float(period) / N, tau, P, _f64(kt), half, _f64(hv), _f64(u), _f64(w),
+                                   None if arg is None else arg.ctypes.data_as(_i32p))
+    if rc:
+        raise RuntimeError("orc_semigroup1_step failed: %d" % rc)
+    return (w, arg) if with_argmin else w
+
+
+def semigroup1_run(u0: np.ndarray, tau: float, P: float, nsteps: int, V: Optional[np.ndarray] = None,
+                   period: float = 1.0, ktab: Optional[np.ndarray] = None) -> np.ndarray:
+    """nsteps steps of the first discrete semigroup (eq. compo)."""
+    u = _c(u0).copy()
+    for _ in range(nsteps):
+        u = semigroup1_step(u, tau, P, V, period, ktab)
+    return u

@@ -391,3 +391,52 @@ def test_adjoint_invariants(orc):
     uT, gu, gc = orc.adjoint(u0, tau, list(P), steps, basis, coef, g)
     assert abs(gu.sum() - g.sum()) < 1e-12
     assert abs(gc[0] - (-steps * tau * g.sum())) < 1e-12
+
+
+# ---- first discrete semigroup (Section 2.2, eq. cost1) --------------------
+def _sg1_inputs(N, seed):
+    return wl.smooth_grid([N], seed) + 0.1 * wl.random_grid([N], seed + 1), wl.smooth_grid([N], seed + 2)
+
+
+def test_semigroup1_without_potential_is_the_sweep(orc):
+    """V = 0: the path integral vanishes and the step is the min-plus sweep,
+    bit for bit (values and argmins)."""
+    u, _ = _sg1_inputs(90, 60)
+    w, a = orc.semigroup1_step(u, 0.05, 0.3, None, with_argmin=True)
+    w0, a0 = orc.sweep(u, 0, 0.05, 0.3)
+    np.testing.assert_array_equal(w, w0)
+    np.testing.assert_array_equal(a, a0)
+
+
+def test_semigroup1_constant_potential(orc):
+    """V = c: every path averages tau c, so the step is the sweep minus tau c
+    (within the rounding of the trapezoid sums)."""
+    u, _ = _sg1_inputs(90, 62)
+    c, tau = 0.7, 0.05
+    w = orc.semigroup1_step(u, tau, -0.2, np.full(90, c))
+    w0, _ = orc.sweep(u, 0, tau, -0.2)
+    assert np.max(np.abs(w - (w0 - tau * c))) <= 1e-14
+
+
+def test_semigroup1_shift_and_reflection(orc):
+    """Shifting u and V shifts the step bit for bit; reflecting them and P
+    (the path's trapezoid sum then runs over the mirrored points in the same
+    order) reflects it bit for bit."""
+    N, tau, P = 96, 0.04, 0.25
+    u, V = _sg1_inputs(N, 64)
+    w = orc.semigroup1_step(u, tau, P, V)
+    r = 17
+    np.testing.assert_array_equal(orc.semigroup1_step(np.roll(u, r), tau, P, np.roll(V, r)), np.roll(w, r))
+    mirror = lambda f: np.roll(f[::-1], 1)   # x -> -x on the periodic grid
+    np.testing.assert_array_equal(orc.semigroup1_step(mirror(u), tau, -P, mirror(V)), mirror(w))
+
+
+def test_semigroup1_order(orc):
+    """Monotone in u, and order-reversing in V (a larger potential lowers
+    every path's action)."""
+    N, tau, P = 80, 0.05, 0.1
+    u, V = _sg1_inputs(N, 66)
+    w = orc.semigroup1_step(u, tau, P, V)
+    du = np.abs(wl.random_grid([N], 70))
+    assert np.all(orc.semigroup1_step(u + du, tau, P, V) >= w)
+    assert np.all(orc.semigroup1_step(u, tau, P, V + du) <= w)
