@@ -190,6 +190,24 @@ lo_status lo_time_kernels(lo_plan_t plan, double* u, int64_t n0, int64_t nsteps,
 lo_status lo_run_decomp(lo_plan_t plan, double* u, int64_t n0, int64_t nsteps, double eta, int32_t window,
                         int64_t* pieces, int64_t* breaks, void* stream);
 
+/* The first discrete semigroup (Section 2.2, eq. cost1, composed as in
+ * eq. compo) on a 1-D plan with a static potential (or none): each step is
+ *     u+(x) = min over lifted y in [x - window, x + window] of
+ *             fl( fl(u(y) + k(x - y)) - I(y, x) ),
+ * k the plan's kinetic cost and I the time integral of V along the straight
+ * path from y to x, by the trapezoid rule over the grid points the path
+ * crosses, on hv = fl(tau V): I = hv(x) when y = x, else
+ * (hv(y)/2 + hv(y+d) + ... + hv(x-d) + hv(x)/2) / m, m = |x - y|, d = sign(x - y).  The potential is inside the cost (no separate potential
+ * step).  Path sums come from prefix sums of hv, so values agree with the
+ * path-order definition to rounding (about N eps max|tau V|), not bit for
+ * bit.  window = 0 takes the plan's whole cost table.  Runs nsteps steps on
+ * u (device [n[0]]).  LO_ERR_WINDOW when a minimiser reached |x - y| = window
+ * (the result may then miss farther minimisers); LO_ERR_UNSUPPORTED unless
+ * the plan is 1-D, not batched and its potential static; LO_ERR_INVALID for
+ * window < 0 or above the plan's table.  Synchronous; allocates its scratch in
+ * the plan on first use. */
+lo_status lo_run_semigroup1(lo_plan_t plan, double* u, int64_t nsteps, int32_t window, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

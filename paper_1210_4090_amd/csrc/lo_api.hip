@@ -50,6 +50,8 @@ struct lo_plan_s {
     double* dhv = nullptr;       // tau*V (static) or the current step's tau*V(t_n)
     double* dc_w = nullptr;      // lo_run_decomp: sweep output [npts]
     unsigned long long* dc_cnt = nullptr;   // lo_run_decomp: pieces, breaks
+    double* sg_q = nullptr;      // lo_run_semigroup1: prefix sums of hv [npts + 1]
+    unsigned* sg_sat = nullptr;  // lo_run_semigroup1: an argmin reached the window's edge
     bool has_v = false;
     bool time_dep = false;
     double dvf[kMaxDim] = {0, 0, 0}, dvb[kMaxDim] = {0, 0, 0};
@@ -168,6 +170,8 @@ void free_plan(lo_plan_t p)
     if (p->tune_u) (void)hipFree(p->tune_u);
     if (p->dc_w) (void)hipFree(p->dc_w);
     if (p->dc_cnt) (void)hipFree(p->dc_cnt);
+    if (p->sg_q) (void)hipFree(p->sg_q);
+    if (p->sg_sat) (void)hipFree(p->sg_sat);
     delete p;
 }
 
@@ -976,6 +980,45 @@ lo_status lo_run_decomp(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, doub
     if (pieces) *pieces = (int64_t)c[0];
     if (breaks) *breaks = (int64_t)c[1];
     return LO_OK;
+}
+
+lo_status lo_run_semigroup1(lo_plan_t p, double* u, int64_t nsteps, int32_t window, void* stream)
+{
+    if (!p || !u || nsteps < 0 || window < 0) return LO_ERR_INVALID;
+    if (p->ndim != 1 || p->nb != 1 || p->time_dep) return LO_ERR_UNSUPPORTED;
+    const int64_t N = p->n[0];
+    const int64_t W = window > 0 ? window : p->kcap[0];
+    if (W > p->kcap[0]) return LO_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->dc_w) {
+        lo_status st = alloc((void**)&p->dc_w, sizeof(double) * (size_t)N);
+        if (!st) st = alloc((void**)&p->dc_cnt, sizeof(unsigned long long) * 2);
+        if (st) return st;
+    }
+    if (!p->sg_q) {
+        lo_status st = alloc((void**)&p->sg_q, sizeof(double) * (size_t)(N + 1));
+        if (!st) st = alloc((void**)&p->sg_sat, sizeof(unsigned));
+        if (st) return st;
+    }
+    const double* hv = p->has_v ? p->dhv : nullptr;
+    if (hv) {
+        // prefix sums of the static tau V table, on the host in grid order
+        std::vector<double> h((size_t)N), q((size_t)N + 1);
+        HIPCHK(hipMemcpyAsync(h.data(), hv, sizeof(double) * (size_t)N, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        q[0] = 0.0;
+        for (int64_t i = 0; i < N; i++) q[(size_t)i + 1] = q[(size_t)i] + h[(size_t)i];
+        HIPCHK(hipMemcpyAsync(p->sg_q, q.data(), sizeof(double) * (size_t)(N + 1), hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipMemsetAsync(p->sg_sat, 0, sizeof(unsigned), s));
+    for (int64_t k = 0; k < nsteps; k++) {
+        HIPCHK(launch_semigroup1(u, p->dc_w, N, (int)W, p->dkt[0] + p->kcap[0], hv, p->sg_q, p->sg_sat, s));
+        HIPCHK(hipMemcpyAsync(u, p->dc_w, sizeof(double) * (size_t)N, hipMemcpyDeviceToDevice, s));
+    }
+    unsigned sat = 0;
+    HIPCHK(hipMemcpyAsync(&sat, p->sg_sat, sizeof(sat), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return sat ? LO_ERR_WINDOW : LO_OK;
 }
 
 lo_status lo_last_diag(lo_plan_t p, int32_t* window_used, int32_t* max_abs_offset)

@@ -131,6 +131,9 @@ hipError_t launch_diff_range(const double* u, const double* snap, int64_t npts, 
 hipError_t launch_synth_hv(const double* basis, const double* coef_dev, int nmodes, int64_t npts,
                            double tau, double* hv, hipStream_t s);
 hipError_t launch_scale(const double* V, double tau, int64_t npts, double* hv, hipStream_t s);
+// One step of the first discrete semigroup (1-D): u -> w, Q the prefix sums of hv ([N + 1]).
+hipError_t launch_semigroup1(const double* u, double* w, int64_t N, int W, const double* kt_centre, const double* hv,
+                             const double* Q, unsigned* sat, hipStream_t s);
 // One step of the decomposition comparison path (1-D): u -> w (sweep) -> u_out = w - hv.
 hipError_t launch_decomp_step(const double* u, double* w, double* u_out, int N, int W, const double* kt_centre,
                               double tol, const double* hv, unsigned long long* counts, hipStream_t s);

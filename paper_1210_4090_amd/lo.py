@@ -195,6 +195,14 @@ class Plan:
                                                    ctypes.byref(breaks), _stream(stream)))
         return pieces.value, breaks.value
 
+    def run_semigroup1(self, u: torch.Tensor, nsteps: int, window: int = 0, stream=None):
+        """nsteps steps of the first discrete semigroup (1-D plans, static V):
+        straight-path action with the trapezoid time integral of V, offsets
+        within [-window, window] (0: the plan's whole table)."""
+        _dev_f64(u, "u", self.shape)
+        check("lo_run_semigroup1", lib().lo_run_semigroup1(self._h, ctypes.c_void_p(u.data_ptr()), int(nsteps),
+                                                           int(window), _stream(stream)))
+
     def kinetic_table(self, axis: int, s0: int, count: int) -> np.ndarray:
         out = np.empty(count, dtype=np.float64)
         check("lo_kinetic_table", lib().lo_kinetic_table(self._h, int(axis), int(s0), int(count),
