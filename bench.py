@@ -100,10 +100,12 @@ def measure_workload(torch, w, method, K, W, steps=None, autotune=False):
             "window_max": wins, "plan": plan, "V": V, "u0": u0}
 
 
-def measure_adjoint(torch, method, every=50, reps=2, autotune=False):
+def measure_adjoint(torch, method, every=50, reps=2, autotune=False, record=False):
     """Differentiation workload (1024^2, 500 steps, 64 Fourier modes of V):
     forward with FP64 checkpoints every `every` steps, then the reverse pass
-    (segment recompute with int16 argmins, reverse sweeps, projection)."""
+    (segment recompute with int16 argmins, reverse sweeps, projection); with
+    record, the forward pass keeps every step's argmins instead (2 GB here)
+    and the reverse pass recomputes nothing."""
     import numpy as np
     from paper_1210_4090_amd import workloads as wl
     from paper_1210_4090_amd.lo import Plan
@@ -118,10 +120,13 @@ def measure_adjoint(torch, method, every=50, reps=2, autotune=False):
         u.copy_(u0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ck = plan.run(u, w.steps, 0, every)
+        ck = plan.run_record(u, w.steps) if record else plan.run(u, w.steps, 0, every)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        plan.backward(ck, w.steps, every, gT)
+        if record:
+            plan.backward_recorded(ck, w.steps, gT)
+        else:
+            plan.backward(ck, w.steps, every, gT)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         if best is None or t2 - t0 < best[0] + best[1]:
@@ -130,7 +135,8 @@ def measure_adjoint(torch, method, every=50, reps=2, autotune=False):
     fwd, bwd = best
     return {"forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3,
             "fwd_adjoint_updates_per_s": w.npts * w.steps / (fwd + bwd),
-            "checkpoint_every": every, "nmodes": int(w.basis.shape[0])}
+            "checkpoint_every": 0 if record else every, "recorded_argmins": bool(record),
+            "nmodes": int(w.basis.shape[0])}
 
 
 def measure_hbar(torch, method, subset=32):
@@ -328,6 +334,8 @@ def main():
         extras["batched_hbar_512"] = measure_hbar(torch, args.method)
         log("batched hbar: %s" % extras["batched_hbar_512"])
         extras["fwd_adjoint_1024^2_500steps"] = measure_adjoint(torch, args.method)
+        extras["fwd_adjoint_1024^2_500steps_recorded_argmins"] = measure_adjoint(torch, args.method, record=True)
+        log("fwd+adjoint, recorded argmins: %s" % extras["fwd_adjoint_1024^2_500steps_recorded_argmins"])
         extras["paper_pendulum_2^18"] = measure_paper_pendulum(torch, args.method)
         log("paper pendulum: %s" % extras["paper_pendulum_2^18"])
         extras["paper_decomposition_pendulum_2^14"] = measure_decomposition(torch)

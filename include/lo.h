@@ -151,6 +151,23 @@ lo_status lo_effective_H(int32_t ninst, const lo_desc* descs, const lo_potential
 lo_status lo_backward(lo_plan_t plan, const double* ckpt, int64_t nsteps, int64_t ckpt_every,
                       const double* grad_uT, double* grad_u0, double* grad_coef, void* stream);
 
+/* Forward run that records every sweep's argmins, for an adjoint without
+ * recomputation: steps n0 .. n0+nsteps-1 on u (device [npts]) as lo_run, and
+ * argmins (device int16 [nsteps][ndim][npts], caller-owned) receives every
+ * step's offsets as lo_step reports them.  Trades 2 ndim bytes a point a step
+ * (2 GB for 500 steps of a 1024^2 grid) for the segment recompute of
+ * lo_backward.  Errors as lo_run; LO_ERR_UNSUPPORTED if an offset exceeds
+ * int16.  Synchronous. */
+lo_status lo_run_record(lo_plan_t plan, double* u, int64_t n0, int64_t nsteps, int16_t* argmins, void* stream);
+
+/* Adjoint of the nsteps-step map from argmins recorded by lo_run_record
+ * (steps 0 .. nsteps-1, device int16 [nsteps][ndim][npts]): gradients as
+ * lo_backward's, without recomputing any step (the same argmins, scattered in
+ * the same order, give the same gradients).  Same arguments and errors as
+ * lo_backward otherwise. */
+lo_status lo_backward_recorded(lo_plan_t plan, const int16_t* argmins, int64_t nsteps, const double* grad_uT,
+                               double* grad_u0, double* grad_coef, void* stream);
+
 const char* lo_status_string(lo_status s);
 
 /* Diagnostics of the last lo_step/lo_run/lo_backward (host arrays [ndim],

@@ -82,6 +82,10 @@ SIGNATURES = {
                                      ctypes.c_void_p]),
     "lo_run_semigroup1": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.c_void_p]),
+    "lo_run_record": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "lo_backward_recorded": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_void_p, _f64p, ctypes.c_void_p]),
 }
 
 

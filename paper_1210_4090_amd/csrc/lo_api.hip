@@ -1187,24 +1187,99 @@ lo_status lo_effective_H(int32_t ninst, const lo_desc* descs, const lo_potential
     return LO_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Scatter layouts of every axis for offsets up to amax[a].
+lo_status scatter_layouts(lo_plan_t p, const uint32_t* amax, ScatterArgs* sa)
+{
+    int dev = 0, lds_max = 65536;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return LO_ERR_HIP;
+    for (int a = 0; a < p->ndim; a++) {
+        AxisGeom g;
+        g.n = p->n[a];
+        g.stride = 1;
+        for (int b = 0; b < a; b++) g.stride *= p->n[b];
+        g.nlines = p->npts / p->n[a];
+        if (!scatter_layout(g, (int)amax[a], (size_t)lds_max, &sa[a])) return LO_ERR_UNSUPPORTED;
+    }
+    return LO_OK;
+}
+
+// Reverse of steps n1-1 .. n0 whose argmins are E[(n - n0)][a][npts]: axes
+// d-1 .. 0, the adjoint of u^{n+1} entering the potential's gradient before
+// the sweeps are undone.  lam ping-pongs between the plan's two buffers.
+lo_status reverse_steps(lo_plan_t p, const int16_t* E, int64_t n0, int64_t n1, const ScatterArgs* sa, int* cur,
+                        bool coef, hipStream_t s)
+{
+    for (int64_t n = n1 - 1; n >= n0; n--) {
+        for (int a = p->ndim - 1; a >= 0; a--) {
+            const int16_t* Ea = E + ((size_t)(n - n0) * p->ndim + a) * p->npts;
+            double* Lam = (coef && a == p->ndim - 1) ? p->bw_Lam : nullptr;
+            HIPCHK(launch_scatter(Ea, p->bw_lam[*cur], p->bw_lam[*cur ^ 1], Lam, sa[a], p->flags, s));
+            *cur ^= 1;
+        }
+    }
+    return LO_OK;
+}
+
+// Gradient outputs and the error report of a reverse pass.
+lo_status finish_backward(lo_plan_t p, int cur, double* grad_u0, double* grad_coef, uint32_t errs, uint32_t* hf,
+                          lo_status st, hipStream_t s)
+{
+    const size_t bytes = sizeof(double) * (size_t)p->npts;
+    if (!st && grad_u0) HIPCHK(hipMemcpyAsync(grad_u0, p->bw_lam[cur], bytes, hipMemcpyDeviceToDevice, s));
+    if (!st && grad_coef) {
+        const int G = project_blocks(p->npts);
+        double* out = p->bw_part + (size_t)p->nmodes * G;
+        HIPCHK(launch_project(p->bw_Lam, p->basis, p->nmodes, p->npts, p->bw_part, out, s));
+        std::vector<double> acc(p->nmodes);
+        HIPCHK(hipMemcpyAsync(acc.data(), out, sizeof(double) * p->nmodes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int m = 0; m < p->nmodes; m++) grad_coef[m] = -p->d.tau * acc[m];
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    uint32_t f0 = 0;
+    HIPCHK(hipMemcpy(&f0, p->flags, sizeof(f0), hipMemcpyDeviceToHost));
+    errs |= f0;
+    hf[0] = errs;
+    for (int i = 0; i < 8; i++) p->hflags[i] = hf[i];
+    p->have_diag = true;
+    p->had_argmin = true;
+    if (st) return st;
+    if (errs & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrAdjointHalo)) return LO_ERR_WINDOW;
+    if (errs & kErrArgRange) return LO_ERR_UNSUPPORTED;
+    return LO_OK;
+}
+
+lo_status check_backward_args(lo_plan_t p, int64_t nsteps, const double* grad_uT, const double* grad_coef)
+{
+    if (!p || !grad_uT || nsteps < 0) return LO_ERR_INVALID;
+    if (grad_coef && (p->nmodes <= 0 || !p->basis)) return LO_ERR_INVALID;
+    if (grad_coef && p->time_dep) return LO_ERR_UNSUPPORTED;
+    return LO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t ckpt_every,
                       const double* grad_uT, double* grad_u0, double* grad_coef, void* stream)
 {
-    if (!p || (!ckpt && nsteps > 0) || !grad_uT || nsteps < 0 || ckpt_every <= 0) return LO_ERR_INVALID;
-    if (grad_coef && (p->nmodes <= 0 || !p->basis)) return LO_ERR_INVALID;
-    if (grad_coef && p->time_dep) return LO_ERR_UNSUPPORTED;
+    lo_status st = check_backward_args(p, nsteps, grad_uT, grad_coef);
+    if (st) return st;
+    if ((!ckpt && nsteps > 0) || ckpt_every <= 0) return LO_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    lo_status st = backward_buffers(p, std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1)),
-                                    grad_coef != nullptr);
+    st = backward_buffers(p, std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1)), grad_coef != nullptr);
     if (st) return st;
     const size_t bytes = sizeof(double) * (size_t)p->npts;
     int cur = 0;
     HIPCHK(hipMemcpyAsync(p->bw_lam[cur], grad_uT, bytes, hipMemcpyDeviceToDevice, s));
     if (grad_coef) HIPCHK(hipMemsetAsync(p->bw_Lam, 0, bytes, s));
-    int dev = 0, lds_max = 65536;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-        return LO_ERR_HIP;
     uint32_t hf[8] = {0};
     uint32_t errs = 0;
     const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
@@ -1233,48 +1308,51 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
             hf[1 + a] = std::max(hf[1 + a], std::max(p->hflags[1 + a], fold_window(f, a)));
             hf[4 + a] = std::max(hf[4 + a], f[4 + a]);
         }
-        // reverse: steps n1-1 .. n0, axes d-1 .. 0; the adjoint of u^{n+1}
-        // enters the potential's gradient before the sweeps are undone
         ScatterArgs sa[kMaxDim];
-        for (int a = 0; a < p->ndim; a++) {
-            AxisGeom g;
-            g.n = p->n[a];
-            g.stride = 1;
-            for (int b = 0; b < a; b++) g.stride *= p->n[b];
-            g.nlines = p->npts / p->n[a];
-            if (!scatter_layout(g, (int)f[4 + a], (size_t)lds_max, &sa[a])) return LO_ERR_UNSUPPORTED;
-        }
-        for (int64_t n = n1 - 1; n >= n0; n--) {
-            for (int a = p->ndim - 1; a >= 0; a--) {
-                const int16_t* E = p->bw_arg + ((size_t)(n - n0) * p->ndim + a) * p->npts;
-                double* Lam = (grad_coef && a == p->ndim - 1) ? p->bw_Lam : nullptr;
-                HIPCHK(launch_scatter(E, p->bw_lam[cur], p->bw_lam[cur ^ 1], Lam, sa[a], p->flags, s));
-                cur ^= 1;
-            }
-        }
+        st = scatter_layouts(p, f + 4, sa);
+        if (!st) st = reverse_steps(p, p->bw_arg, n0, n1, sa, &cur, grad_coef != nullptr, s);
     }
-    if (!st && grad_u0) HIPCHK(hipMemcpyAsync(grad_u0, p->bw_lam[cur], bytes, hipMemcpyDeviceToDevice, s));
-    if (!st && grad_coef) {
-        const int G = project_blocks(p->npts);
-        double* out = p->bw_part + (size_t)p->nmodes * G;
-        HIPCHK(launch_project(p->bw_Lam, p->basis, p->nmodes, p->npts, p->bw_part, out, s));
-        std::vector<double> acc(p->nmodes);
-        HIPCHK(hipMemcpyAsync(acc.data(), out, sizeof(double) * p->nmodes, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int m = 0; m < p->nmodes; m++) grad_coef[m] = -p->d.tau * acc[m];
+    return finish_backward(p, cur, grad_u0, grad_coef, errs, hf, st, s);
+}
+
+lo_status lo_run_record(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int16_t* argmins, void* stream)
+{
+    if (!p || !u || nsteps < 0 || (!argmins && nsteps > 0)) return LO_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    lo_status st = prologue(p, u, n0, s);
+    for (int64_t k = 0; k < nsteps && !st; k++) {
+        if (k > 0 && k % kGraphSteps == 0) st = adapt_from_flags(p, s);
+        if (!st) st = enqueue_step(p, u, n0 + k, argmins + (size_t)k * p->ndim * p->npts, s);
     }
-    HIPCHK(hipStreamSynchronize(s));
-    uint32_t f0 = 0;
-    HIPCHK(hipMemcpy(&f0, p->flags, sizeof(f0), hipMemcpyDeviceToHost));
-    errs |= f0;
-    hf[0] = errs;
-    for (int i = 0; i < 8; i++) p->hflags[i] = hf[i];
-    p->have_diag = true;
-    p->had_argmin = true;
     if (st) return st;
-    if (errs & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrAdjointHalo)) return LO_ERR_WINDOW;
-    if (errs & kErrArgRange) return LO_ERR_UNSUPPORTED;
-    return LO_OK;
+    return finish(p, s, true);
+}
+
+lo_status lo_backward_recorded(lo_plan_t p, const int16_t* argmins, int64_t nsteps, const double* grad_uT,
+                               double* grad_u0, double* grad_coef, void* stream)
+{
+    lo_status st = check_backward_args(p, nsteps, grad_uT, grad_coef);
+    if (st) return st;
+    if (!argmins && nsteps > 0) return LO_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    st = backward_buffers(p, 1, grad_coef != nullptr);
+    if (st) return st;
+    const size_t bytes = sizeof(double) * (size_t)p->npts;
+    int cur = 0;
+    HIPCHK(hipMemcpyAsync(p->bw_lam[cur], grad_uT, bytes, hipMemcpyDeviceToDevice, s));
+    if (grad_coef) HIPCHK(hipMemsetAsync(p->bw_Lam, 0, bytes, s));
+    HIPCHK(hipMemsetAsync(p->flags, 0, sizeof(uint32_t) * kFlagWords, s));
+    // the largest offset of each axis sizes the scatter tiles' halos
+    HIPCHK(launch_absmax16(argmins, nsteps, p->ndim, p->npts, p->flags + 4, s));
+    uint32_t f[kFlagWords];
+    HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(f), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    uint32_t hf[8] = {0};
+    for (int a = 0; a < p->ndim; a++) hf[4 + a] = f[4 + a];
+    ScatterArgs sa[kMaxDim];
+    st = scatter_layouts(p, f + 4, sa);
+    if (!st) st = reverse_steps(p, argmins, 0, nsteps, sa, &cur, grad_coef != nullptr, s);
+    return finish_backward(p, cur, grad_u0, grad_coef, 0, hf, st, s);
 }
 
 }  // extern "C"

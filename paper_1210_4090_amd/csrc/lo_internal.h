@@ -166,6 +166,8 @@ bool scatter_layout(const AxisGeom& g, int h, size_t lds_max, ScatterArgs* a);
 hipError_t launch_scatter(const int16_t* E, const double* lam, double* out, double* Lam, const ScatterArgs& a,
                           uint32_t* flags, hipStream_t s);
 int project_blocks(int64_t npts);
+// Largest |argmin offset| of each axis over [steps][ndim][npts] int16 offsets (atomicMax into out[a]).
+hipError_t launch_absmax16(const int16_t* E, int64_t steps, int ndim, int64_t npts, uint32_t* out, hipStream_t s);
 hipError_t launch_project(const double* Lam, const double* basis, int M, int64_t npts, double* partial,
                           double* out, hipStream_t s);
 

@@ -195,6 +195,30 @@ class Plan:
                                                    ctypes.byref(breaks), _stream(stream)))
         return pieces.value, breaks.value
 
+    def run_record(self, u: torch.Tensor, nsteps: int, n0: int = 0, stream=None) -> torch.Tensor:
+        """Run nsteps steps recording every sweep's int16 argmins; returns the
+        record ([nsteps, ndim, *grid]) for backward_recorded."""
+        _dev_f64(u, "u", self.shape)
+        E = torch.empty((max(int(nsteps), 0), self.ndim) + self.shape, dtype=torch.int16, device=u.device)
+        check("lo_run_record", lib().lo_run_record(self._h, ctypes.c_void_p(u.data_ptr()), int(n0), int(nsteps),
+                                                   ctypes.c_void_p(E.data_ptr() if E.numel() else 0),
+                                                   _stream(stream)))
+        return E
+
+    def backward_recorded(self, E: torch.Tensor, nsteps: int, grad_uT: torch.Tensor, want_u0: bool = True,
+                          want_coef: bool = True, stream=None):
+        """Adjoint from a record of run_record: (grad_u0 tensor or None, grad_coef ndarray or None)."""
+        if E.dtype != torch.int16 or not E.is_contiguous() or tuple(E.shape) != (int(nsteps), self.ndim) + self.shape:
+            raise ValueError("E must be the contiguous int16 record of run_record")
+        _dev_f64(grad_uT, "grad_uT", self.shape)
+        gu = torch.empty_like(grad_uT) if want_u0 else None
+        gc = np.zeros(max(self.nmodes, 1), dtype=np.float64) if (want_coef and self.nmodes > 0) else None
+        check("lo_backward_recorded", lib().lo_backward_recorded(
+            self._h, ctypes.c_void_p(E.data_ptr() if E.numel() else 0), int(nsteps),
+            ctypes.c_void_p(grad_uT.data_ptr()), ctypes.c_void_p(gu.data_ptr() if gu is not None else 0),
+            gc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if gc is not None else None, _stream(stream)))
+        return gu, (gc[: self.nmodes] if gc is not None else None)
+
     def run_semigroup1(self, u: torch.Tensor, nsteps: int, window: int = 0, stream=None):
         """nsteps steps of the first discrete semigroup (1-D plans, static V):
         straight-path action with the trapezoid time integral of V, offsets
@@ -234,14 +258,16 @@ class LaxOleinik(torch.autograd.Function):
     """u(T) = T^N u0 for V = sum_m coef_m basis_m, differentiable in u0 and coef.
 
     forward(u0, coef, plan, nsteps, ckpt_every); gradients come from the
-    library's argmin-scatter adjoint (lo_backward) recomputing segments of
-    ckpt_every steps from FP64 checkpoints."""
+    library's argmin-scatter adjoint: lo_backward recomputing segments of
+    ckpt_every steps from FP64 checkpoints, or, with ckpt_every = 0, every
+    step's argmins recorded by the forward pass (lo_run_record,
+    lo_backward_recorded: no recomputation, 2 ndim bytes a point a step)."""
 
     @staticmethod
     def forward(ctx, u0: torch.Tensor, coef: torch.Tensor, plan: Plan, nsteps: int, ckpt_every: int):
         plan.set_coef(coef.detach().cpu().numpy())
         u = u0.detach().clone()
-        ck = plan.run(u, nsteps, 0, ckpt_every)
+        ck = plan.run_record(u, nsteps) if ckpt_every == 0 else plan.run(u, nsteps, 0, ckpt_every)
         ctx.plan = plan
         ctx.nsteps = nsteps
         ctx.ckpt_every = ckpt_every
@@ -251,8 +277,12 @@ class LaxOleinik(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_uT: torch.Tensor):
         ck, coef = ctx.saved_tensors
-        gu, gc = ctx.plan.backward(ck, ctx.nsteps, ctx.ckpt_every, grad_uT.contiguous(),
-                                   want_u0=ctx.needs_input_grad[0], want_coef=ctx.needs_input_grad[1])
+        if ctx.ckpt_every == 0:
+            gu, gc = ctx.plan.backward_recorded(ck, ctx.nsteps, grad_uT.contiguous(),
+                                                want_u0=ctx.needs_input_grad[0], want_coef=ctx.needs_input_grad[1])
+        else:
+            gu, gc = ctx.plan.backward(ck, ctx.nsteps, ctx.ckpt_every, grad_uT.contiguous(),
+                                       want_u0=ctx.needs_input_grad[0], want_coef=ctx.needs_input_grad[1])
         gcoef = None
         if gc is not None:
             gcoef = torch.as_tensor(gc, dtype=coef.dtype, device=coef.device)

@@ -234,3 +234,51 @@ def test_autotuned_plan_same_gradients(torch_dev):
     assert np.array_equal(res[0][0], res[1][0])
     assert np.array_equal(res[0][1], res[1][1])
     assert np.array_equal(res[0][2], res[1][2])
+
+
+@pytest.mark.parametrize("method", ["brute", "fast"])
+@pytest.mark.parametrize("case", [0, 2, 4])
+def test_recorded_argmins_adjoint(torch_dev, orc, case, method):
+    """Forward pass recording every step's argmins (lo_run_record), then the
+    reverse pass without recomputation (lo_backward_recorded): the same
+    forward result and the same gradients as the checkpointed adjoint, bit
+    for bit, and the oracle's adjoint within the usual tolerance."""
+    torch = torch_dev
+    from paper_1210_4090_amd.lo import Plan
+    n, tau, P, steps, every = CASES[case]
+    print_case("recorded adjoint", n, steps, method)
+    basis = _basis(n, 6, 100 + case)
+    coef = np.random.default_rng(200 + case).standard_normal(basis.shape[0]) * 0.5
+    u0 = wl.smooth_grid(list(n), 300 + case)
+    gT = np.random.default_rng(400 + case).standard_normal(u0.shape)
+    uT, gu, gc, _ = _run_adjoint(torch, n, tau, P, basis, coef, u0, gT, steps, every, method)
+    p = Plan(n, tau, P, basis=_gpu(torch, basis), coef=coef, method=method)
+    u = _gpu(torch, u0)
+    E = p.run_record(u, steps)
+    gu2, gc2 = p.backward_recorded(E, steps, _gpu(torch, gT))
+    np.testing.assert_array_equal(u.cpu().numpy(), uT)
+    np.testing.assert_array_equal(gu2.cpu().numpy(), gu)
+    np.testing.assert_array_equal(gc2, gc)
+    _, ogu, ogc = orc.adjoint(u0, tau, list(P), steps, basis, coef, gT)
+    assert _rel(gu2.cpu().numpy(), ogu) <= ADJ_TOL
+    assert _rel(gc2, ogc) <= ADJ_TOL
+
+
+def test_recorded_argmins_autograd(torch_dev):
+    """LaxOleinik with ckpt_every = 0 (recorded argmins) gives the
+    checkpointed gradients."""
+    torch = torch_dev
+    from paper_1210_4090_amd.lo import Plan, LaxOleinik
+    n, tau, P, steps = (48, 40), 0.04, (0.2, -0.1), 16
+    basis = _gpu(torch, _basis(n, 6, 150))
+    grads = []
+    for every in (4, 0):
+        p = Plan(n, tau, P, basis=basis, coef=np.zeros(6), method="fast")
+        u0 = _gpu(torch, wl.smooth_grid(list(n), 151)).requires_grad_(True)
+        coef = torch.tensor(np.random.default_rng(152).standard_normal(6) * 0.5, dtype=torch.float64,
+                            requires_grad=True)
+        uT = LaxOleinik.apply(u0, coef, p, steps, every)
+        (uT * uT).sum().backward()
+        grads.append((u0.grad.cpu().numpy(), coef.grad.cpu().numpy()))
+    np.testing.assert_array_equal(grads[0][0], grads[1][0])
+    np.testing.assert_array_equal(grads[0][1], grads[1][1])
