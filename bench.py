@@ -266,6 +266,23 @@ def cpu_baseline(w, nsteps=30):
             % (nsteps, w.name, dt)}
 
 
+def _only_3d(torch, method):
+    from paper_1210_4090_amd import workloads as wl
+    m = measure_workload(torch, wl.config3(), method, 2, 1)
+    return {"updates_per_s": m["rate"], "ms_per_run": m["ms_per_run"], "kernel_ms": m["kernel_ms"],
+            "all_axis_GBs": m["all_axis_GBs"]}
+
+
+# one secondary workload at a time (python bench.py --only NAME), for profiling runs
+ONLY = {
+    "3d": _only_3d,
+    "hbar": lambda torch, method: measure_hbar(torch, method),
+    "adjoint": lambda torch, method: measure_adjoint(torch, method, reps=1),
+    "adjoint_recorded": lambda torch, method: measure_adjoint(torch, method, reps=1, record=True),
+    "pendulum": lambda torch, method: measure_paper_pendulum(torch, method, reps=1),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +291,9 @@ def main():
     ap.add_argument("--method", default="fast", choices=["fast", "brute"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
+    ap.add_argument("--only", choices=sorted(ONLY), default=None,
+                    help="measure one secondary workload and print its figures (for profiling runs); no "
+                         "headline line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -285,6 +305,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.only:
+        print(json.dumps({"workload": args.only, "figures": ONLY[args.only](torch, args.method)}), flush=True)
+        return
     w = wl.config2()
     log("workload %s steps=%d method=%s K=%d W=%d" % (w.name, w.steps, args.method, args.steps, args.warmup))
     m = measure_workload(torch, w, args.method, args.steps, args.warmup)
