@@ -480,8 +480,8 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
 // then the whole block works on one line) x R targets [r0, r0 + R) (+ target
 // r0 + R for the forward differences of the output), lines of any stride.
 // ---------------------------------------------------------------------------
-template <int EPI, int ARG, int C, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict__ in, double* __restrict__ out,
+template <int EPI, int ARG, int C, bool GEN, int BS>
+__global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in, double* __restrict__ out,
                                                        const double* __restrict__ kc, SweepArgs a, ClaimLds L,
                                                        double inv2c, double pofs)
 {
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
     const int NT = Rt + 1;
 
     const int c = (int)threadIdx.x % C;    // line of this thread
-    const int q = (int)threadIdx.x / C;    // rank among the line's 16 threads
+    const int q = (int)threadIdx.x / C;    // rank among the line's BS / C threads
     const int line = lb * C + c;
     const bool lok = line < a.g.nlines;
     const int ln = lok ? line : 0;
@@ -532,14 +532,14 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
     // KT[i] = k(sb + i), i < 2 KH + 1: the window's band (a convex table's
     // crossings also read k(smin - 1))
     const int g = GEN ? 1 : 0, sb = smin - g;
-    for (int i = threadIdx.x; i < 2 * KH + 1; i += kBlock) {
+    for (int i = threadIdx.x; i < 2 * KH + 1; i += BS) {
         const int s = sb + i;
         KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
     }
     const bool fast = smax - sb <= 2 * KH;
     const double* K = KT - sb;   // K[s] = k(s), s in [sb, smax]
     const double gsl = a.kslack;
-    for (int t = q; t < NT; t += kBlock / C) {
+    for (int t = q; t < NT; t += BS / C) {
         W[t * kKeyStride + c] = INFINITY;
         if (ARG) A[t * kKeyStride + c] = 0x7fffffff;
     }
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
         const int pA = r0 - wp, pB = r0 + NT - 1 + wm;
         const int nch = (pB - pA + kCh) / kCh;
         for (int pass = 0; pass < (ARG ? 2 : 1); pass++) {
-            for (int ch = q; ch < nch && lok; ch += kBlock / C) {
+            for (int ch = q; ch < nch && lok; ch += BS / C) {
                 const int p0 = pA + ch * kCh;
                 double uu[kCh + 2];
                 int r = (p0 - 1) % N;
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
             for (int blo = smin; blo <= smax; blo += max(2 * KH + 1 - g, 1)) {
                 const int bhi = min(blo + max(2 * KH - g, 0), smax);
                 __syncthreads();
-                for (int i = threadIdx.x; i < 2 * KH + 1; i += kBlock) {
+                for (int i = threadIdx.x; i < 2 * KH + 1; i += BS) {
                     const int s = blo - g + i;
                     KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
                 }
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
                 // sources that reach the targets with an offset of the window and of the band
                 const int pA = max(r0 - wp, r0 - bhi), pB = min(r0 + NT - 1 + wm, r0 + NT - 1 - blo);
                 const int nch = (pB - pA + 2) / 2;
-                for (int ch = q; ch < nch && lok; ch += kBlock / C) {
+                for (int ch = q; ch < nch && lok; ch += BS / C) {
                     const int p0 = pA + 2 * ch;
                     double u4[4];
                     int r = (p0 - 1) % N;
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
         const double* __restrict__ hv = EPI ? a.hv + lbase + (int64_t)S * r0 : nullptr;
         int16_t* am = (ARG && a.argmin) ? a.argmin + lbase + (int64_t)S * r0 : nullptr;
         int off = S * q;
-        for (int t = q; t < Rt; t += kBlock / C) {
+        for (int t = q; t < Rt; t += BS / C) {
             const double x = W[t * kKeyStride + c];
             bad |= !(x < INFINITY);
             const double z = EPI ? x - hv[off] : x;
@@ -628,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_claim_tile(const double* __restrict_
                 amax = max(amax, abs(e));
             }
             if (a.stats_out) fold_stats<EPI>(st, x, W[(t + 1) * kKeyStride + c], z);
-            off += S * (kBlock / C);
+            off += S * (BS / C);
         }
     }
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
@@ -664,19 +664,28 @@ ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg, int r
 
 template <int ROW>
 hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, const ClaimLds& L, double inv2c,
-                          double pofs, int64_t grid, hipStream_t s)
+                          double pofs, int64_t grid, bool wide, hipStream_t s)
 {
     const size_t lds = claim_lds_bytes(L);
     const bool arg = a.argmin != nullptr;
     const bool epi = a.hv != nullptr;
-#define LO_CLAIM_LAUNCH_G(K, E, A, G)                                                                          \
+#define LO_CLAIM_LAUNCH_B(K, E, A, G, B)                                                                       \
     do {                                                                                                        \
         if (L.C == 1)                                                                                           \
-            hipLaunchKernelGGL((K<E, A, 1, G>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in, out,       \
+            hipLaunchKernelGGL((K<E, A, 1, G, B>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, in, out,         \
                                a.kin.k, a, L, inv2c, pofs);                                                     \
         else                                                                                                    \
-            hipLaunchKernelGGL((K<E, A, kTileLines, G>), dim3((unsigned)grid, a.nb), dim3(kBlock), lds, s, in,   \
+            hipLaunchKernelGGL((K<E, A, kTileLines, G, B>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, in,     \
                                out, a.kin.k, a, L, inv2c, pofs);                                                \
+    } while (0)
+#define LO_CLAIM_LAUNCH_G(K, E, A, G)                                                                          \
+    do {                                                                                                        \
+        if constexpr (A == 0) {                                                                                 \
+            if (wide) LO_CLAIM_LAUNCH_B(K, E, A, G, 2 * kBlock);                                                \
+            else LO_CLAIM_LAUNCH_B(K, E, A, G, kBlock);                                                         \
+        } else {                                                                                                \
+            LO_CLAIM_LAUNCH_B(K, E, A, G, kBlock);                                                              \
+        }                                                                                                       \
     } while (0)
 #define LO_CLAIM_LAUNCH(K, E, A)                                                                                \
     do {                                                                                                        \
@@ -715,6 +724,7 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
     }
 #undef LO_CLAIM_LAUNCH
 #undef LO_CLAIM_LAUNCH_G
+#undef LO_CLAIM_LAUNCH_B
 #undef LO_ROW_LAUNCH
 #undef LO_ROW_LAUNCH_CH
 #undef LO_ROW_LAUNCH_G
@@ -734,20 +744,26 @@ hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double
                        hipStream_t s)
 {
     (void)cq;
-    const int row_ch = a.row_ch == 4 ? 4 : 8;
+    const int C = fast_tile_lines(a.g.nlines);
+    const bool arg = a.argmin != nullptr;
+    // A grid of few tiles (two blocks of 256 threads a CU or fewer) leaves the
+    // SIMDs short of waves: plain sweeps then take blocks of 512 threads (rows:
+    // 4 points a thread).  Argmin sweeps keep 256 (their two passes ran slower
+    // with 512).
+    const int64_t nr = a.kind == kKindRow ? std::max<int64_t>(1, 2048 / a.g.n) : 1;
+    const int64_t tiles = a.kind == kKindRow
+                              ? (a.g.nlines + nr - 1) / nr
+                              : ((a.g.n + a.tile_rows - 1) / a.tile_rows) * ((a.g.nlines + C - 1) / C);
+    const bool few = !arg && tiles * a.nb * 2 <= a.grid_cap;
+    const int row_ch = a.row_ch == 4 || (few && a.kind == kKindRow) ? 4 : 8;
     SweepArgs b = a;
     b.row_ch = row_ch;
-    const int C = fast_tile_lines(a.g.nlines);
-    const ClaimLds L = claim_layout(a.kind, a.g.n, a.tile_rows, a.halo, a.argmin != nullptr, row_ch, C);
+    const ClaimLds L = claim_layout(a.kind, a.g.n, a.tile_rows, a.halo, arg, row_ch, C);
     // ROW: persistent blocks, about grid_cap in all (instances included), each
     // walking several tiles so that its fixed costs are amortised
     const int64_t cap = std::max(1, a.grid_cap / std::max(1, a.nb));
-    if (a.kind == kKindRow) {
-        const int64_t tiles = (a.g.nlines + L.nr - 1) / L.nr;
-        return launch_claim_t<1>(in, out, b, L, inv2c, pofs, std::min(tiles, cap), s);
-    }
-    const int64_t tiles = ((a.g.n + a.tile_rows - 1) / a.tile_rows) * ((a.g.nlines + C - 1) / C);
-    return launch_claim_t<0>(in, out, b, L, inv2c, pofs, tiles, s);
+    if (a.kind == kKindRow) return launch_claim_t<1>(in, out, b, L, inv2c, pofs, std::min(tiles, cap), false, s);
+    return launch_claim_t<0>(in, out, b, L, inv2c, pofs, tiles, few, s);
 }
 
 }  // namespace lo
