@@ -37,7 +37,7 @@ def sweep_bytes(ndim: int, npts: int):
 
 
 # kernel that sweeps axis a of the 2-D headline workload on the fast path
-FAST_2D_KERNELS = {0: "k_claim_row<0,0,8,256,false>", 1: "k_claim_tile<1,0,16,false,256>"}
+FAST_2D_KERNELS = {0: "k_claim_row<0,0,8,256,false>", 1: "k_claim_tile<1,0,16,false,256,16>"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "claim_sweeps_2d_2048sq_hbm_traffic.txt")
 
 

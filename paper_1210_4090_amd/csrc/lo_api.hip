@@ -446,9 +446,11 @@ int choose_halo(lo_plan_t p, int a, int W)
     H = (H + 7) / 8 * 8;
     H = std::max(8, std::min(H, p->halo_max[a]));
     // fast tiles: longer tiles when the window's halo is wide (fewer halo
-    // sources per target), shorter ones keep more blocks resident otherwise
+    // sources per target), shorter ones keep more blocks resident otherwise;
+    // the last axis (potential step) always takes the longer tiles, whose
+    // blocks load their tau V values before the claims
     if (p->fast[a] && p->kind[a] == kKindTile)
-        p->tile_rows[a] = p->tile_fix[a] > 0 ? p->tile_fix[a] : tile_len(p, a, H >= 40);
+        p->tile_rows[a] = p->tile_fix[a] > 0 ? p->tile_fix[a] : tile_len(p, a, H >= 40 || a == p->ndim - 1);
     return H;
 }
 

@@ -68,6 +68,7 @@ using namespace dev;
 constexpr int kCh = 8;           // sources per chunk (tile kernel)
 constexpr int kRowPoints = 2048; // row kernel: points per tile (points per thread x threads)
 constexpr int kTileLines = 16;   // TILE: lines side by side (1 for axes with fewer lines)
+constexpr int kPfTile = 16;      // TILE with the potential step: outputs a thread prefetches tau V for
 constexpr double kEps = 1e-6;    // claim widening, in cells
 
 // skewed LDS slot of key x for chunks of CH points: one pad slot per chunk,
@@ -479,8 +480,10 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
 // TILE kernel: C lines side by side (16, or 1 for an axis with fewer lines:
 // then the whole block works on one line) x R targets [r0, r0 + R) (+ target
 // r0 + R for the forward differences of the output), lines of any stride.
+// BS threads, BS / C per line.  PF > 0 (the potential step, R = PF BS / C):
+// each thread loads the tau V values of its PF outputs before the claims.
 // ---------------------------------------------------------------------------
-template <int EPI, int ARG, int C, bool GEN, int BS>
+template <int EPI, int ARG, int C, bool GEN, int BS, int PF>
 __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in, double* __restrict__ out,
                                                        const double* __restrict__ kc, SweepArgs a, ClaimLds L,
                                                        double inv2c, double pofs)
@@ -542,6 +545,18 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
     for (int t = q; t < NT; t += BS / C) {
         W[t * kKeyStride + c] = INFINITY;
         if (ARG) A[t * kKeyStride + c] = 0x7fffffff;
+    }
+    // PF > 0 (potential step, tiles of PF (BS / C) targets): the tau V values
+    // of this thread's outputs are loaded now, so that their latency passes
+    // during the claims
+    double hvp[PF > 0 ? PF : 1];
+    if (PF > 0 && lok) {
+        const double* __restrict__ h = a.hv + lbase + (int64_t)S * r0;
+#pragma unroll
+        for (int i = 0; i < PF; i++) {
+            const int t = q + i * (BS / C);
+            hvp[i] = t < Rt ? h[(int64_t)S * t] : 0.0;
+        }
     }
     __syncthreads();
 
@@ -617,18 +632,33 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
         const double* __restrict__ hv = EPI ? a.hv + lbase + (int64_t)S * r0 : nullptr;
         int16_t* am = (ARG && a.argmin) ? a.argmin + lbase + (int64_t)S * r0 : nullptr;
         int off = S * q;
-        for (int t = q; t < Rt; t += BS / C) {
-            const double x = W[t * kKeyStride + c];
-            bad |= !(x < INFINITY);
-            const double z = EPI ? x - hv[off] : x;
-            dst[off] = z;
-            if (ARG && am) {
-                const int e = A[t * kKeyStride + c];
-                am[off] = (int16_t)e;
-                amax = max(amax, abs(e));
+        if (PF > 0) {
+#pragma unroll
+            for (int i = 0; i < PF; i++) {
+                const int t = q + i * (BS / C);
+                if (t < Rt) {
+                    const double x = W[t * kKeyStride + c];
+                    bad |= !(x < INFINITY);
+                    const double z = x - hvp[i];
+                    dst[off] = z;
+                    if (a.stats_out) fold_stats<EPI>(st, x, W[(t + 1) * kKeyStride + c], z);
+                }
+                off += S * (BS / C);
             }
-            if (a.stats_out) fold_stats<EPI>(st, x, W[(t + 1) * kKeyStride + c], z);
-            off += S * (BS / C);
+        } else {
+            for (int t = q; t < Rt; t += BS / C) {
+                const double x = W[t * kKeyStride + c];
+                bad |= !(x < INFINITY);
+                const double z = EPI ? x - hv[off] : x;
+                dst[off] = z;
+                if (ARG && am) {
+                    const int e = A[t * kKeyStride + c];
+                    am[off] = (int16_t)e;
+                    amax = max(amax, abs(e));
+                }
+                if (a.stats_out) fold_stats<EPI>(st, x, W[(t + 1) * kKeyStride + c], z);
+                off += S * (BS / C);
+            }
         }
     }
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
@@ -672,10 +702,17 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
 #define LO_CLAIM_LAUNCH_B(K, E, A, G, B)                                                                       \
     do {                                                                                                        \
         if (L.C == 1)                                                                                           \
-            hipLaunchKernelGGL((K<E, A, 1, G, B>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, in, out,         \
+            hipLaunchKernelGGL((K<E, A, 1, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, in, out,      \
                                a.kin.k, a, L, inv2c, pofs);                                                     \
-        else                                                                                                    \
-            hipLaunchKernelGGL((K<E, A, kTileLines, G, B>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, in,     \
+        else if constexpr (E == 1 && A == 0 && B == kBlock) {                                                   \
+            if (a.tile_rows == kPfTile * (kBlock / kTileLines))                                                 \
+                hipLaunchKernelGGL((K<E, A, kTileLines, G, B, kPfTile>), dim3((unsigned)grid, a.nb), dim3(B),   \
+                                   lds, s, in, out, a.kin.k, a, L, inv2c, pofs);                                \
+            else                                                                                                \
+                hipLaunchKernelGGL((K<E, A, kTileLines, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, \
+                                   in, out, a.kin.k, a, L, inv2c, pofs);                                        \
+        } else                                                                                                  \
+            hipLaunchKernelGGL((K<E, A, kTileLines, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, in,  \
                                out, a.kin.k, a, L, inv2c, pofs);                                                \
     } while (0)
 #define LO_CLAIM_LAUNCH_G(K, E, A, G)                                                                          \
