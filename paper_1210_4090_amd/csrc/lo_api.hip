@@ -655,7 +655,8 @@ lo_status backward_buffers(lo_plan_t p, int64_t steps, bool coef)
 // candidate shape on a copy of u and keep, per axis, the shape whose sweep
 // was fastest.  Every shape computes the same values (the minimum over a
 // target's claimants does not depend on how sources are grouped), so the
-// choice only affects speed.
+// choice only affects speed.  The last axis keeps its 256-target tiles (its
+// sweep prefetches tau V for them).
 constexpr int kTuneSteps = 8;
 
 lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
@@ -677,7 +678,7 @@ lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
     for (int ci = 0; ci < 2 && !st; ci++) {
         for (int ri = 0; ri < 2 && !st; ri++) {
             for (int a = 0; a < p->ndim; a++) {
-                if (p->kind[a] == kKindTile) p->tile_fix[a] = tile_len(p, a, ri == 1);
+                if (p->kind[a] == kKindTile) p->tile_fix[a] = tile_len(p, a, ri == 1 || a == p->ndim - 1);
                 else p->row_ch[a] = kC[ci];
             }
             if (hipMemcpyAsync(p->tune_u, u, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) st = LO_ERR_HIP;
@@ -699,7 +700,7 @@ lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
     for (int a = 0; a < p->ndim; a++) {
         if (p->kind[a] == kKindTile) {
             const double t128 = ms[0][0][a] + ms[1][0][a], t256 = ms[0][1][a] + ms[1][1][a];
-            p->tile_fix[a] = tile_len(p, a, t256 < t128);
+            p->tile_fix[a] = tile_len(p, a, t256 < t128 || a == p->ndim - 1);
         } else {
             const double c8 = ms[0][0][a] + ms[0][1][a], c4 = ms[1][0][a] + ms[1][1][a];
             p->row_ch[a] = c4 < c8 ? 4 : 8;

@@ -71,10 +71,10 @@ constexpr int kTileLines = 16;   // TILE: lines side by side (1 for axes with fe
 constexpr int kPfTile = 16;      // TILE with the potential step: outputs a thread prefetches tau V for
 constexpr double kEps = 1e-6;    // claim widening, in cells
 
-// skewed LDS slot of key x for chunks of CH points: one pad slot per chunk,
-// so lanes that walk chunk-strided keys hit distinct banks
+// skewed LDS slot of key x >= 0 for chunks of CH points: one pad slot per
+// chunk, so lanes that walk chunk-strided keys hit distinct banks
 template <int CH>
-__device__ __forceinline__ int skc(int x) { return x + x / CH; }
+__device__ __forceinline__ int skc(int x) { return x + (int)((unsigned)x / CH); }
 
 }  // namespace
 
@@ -251,6 +251,7 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
     const int p0 = ((int)threadIdx.x - r * cpr) * CH;
     const bool act = r < nr;
     const int g0 = r * N + p0;                    // first key of this thread (unskewed)
+    const int gs = skc<CH>(g0);                   // its slot: g0 is a multiple of CH, so key g0 + k is at gs + k
     double* KT = sm;
     double* W = KT + (2 * KH + 1);
     int* A = (int*)(W + L.RS);
@@ -290,7 +291,7 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
         if (!ok) return;
         double x[CH + 1];
 #pragma unroll
-        for (int k = 0; k < CH; k++) x[k] = W[skc<CH>(g0 + k)];
+        for (int k = 0; k < CH; k++) x[k] = W[gs + k];
         x[CH] = W[skc<CH>(kbase + (p0 + CH == N ? 0 : p0 + CH))];
         double z[CH];
         if (EPI) {
@@ -317,7 +318,7 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
             int16_t* am = a.argmin + row * N + p0;
 #pragma unroll
             for (int k = 0; k < CH; k++) {
-                const int e = A[skc<CH>(g0 + k)];
+                const int e = A[gs + k];
                 am[k] = (int16_t)e;
                 amax = max(amax, abs(e));
             }
@@ -333,8 +334,8 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
             if (ok) {
 #pragma unroll
                 for (int k = 0; k < CH; k++) {
-                    W[skc<CH>(g0 + k)] = INFINITY;
-                    if (ARG) A[skc<CH>(g0 + k)] = 0x7fffffff;
+                    W[gs + k] = INFINITY;
+                    if (ARG) A[gs + k] = 0x7fffffff;
                 }
             }
             for (int pass = 0; pass < (ARG ? 2 : 1); pass++) {
@@ -389,8 +390,8 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
                 uu[CH + 1] = src[p0 + CH == N ? 0 : p0 + CH];
 #pragma unroll
                 for (int k = 0; k < CH; k++) {
-                    W[skc<CH>(g0 + k)] = INFINITY;
-                    if (ARG) A[skc<CH>(g0 + k)] = 0x7fffffff;
+                    W[gs + k] = INFINITY;
+                    if (ARG) A[gs + k] = 0x7fffffff;
                 }
             }
             __syncthreads();
@@ -422,8 +423,8 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
                             }
                             if (++j == N) j = 0;
                         }
-                        W[skc<CH>(g0 + k)] = best;
-                        if (ARG) A[skc<CH>(g0 + k)] = arg;
+                        W[gs + k] = best;
+                        if (ARG) A[gs + k] = arg;
                     }
                 }
                 __syncthreads();
@@ -431,7 +432,7 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
             if (ok) {
                 double x[CH + 1];
 #pragma unroll
-                for (int k = 0; k < CH; k++) x[k] = W[skc<CH>(g0 + k)];
+                for (int k = 0; k < CH; k++) x[k] = W[gs + k];
                 x[CH] = W[skc<CH>(kbase + (p0 + CH == N ? 0 : p0 + CH))];
                 double z[CH];
                 if (EPI) {
@@ -458,7 +459,7 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
                     int16_t* am = a.argmin + row * N + p0;
 #pragma unroll
                     for (int k = 0; k < CH; k++) {
-                        const int e = A[skc<CH>(g0 + k)];
+                        const int e = A[gs + k];
                         am[k] = (int16_t)e;
                         amax = max(amax, abs(e));
                     }
