@@ -428,17 +428,6 @@ lo_status upload_winparams(lo_plan_t p)
     return LO_OK;
 }
 
-// The device's one-sided window search, on the host table (for sizing halos).
-int host_side(const std::vector<double>& t, int64_t kcap, int dir, double D, double sbase, bool level)
-{
-    const double k0 = t[kcap];
-    for (int64_t s = 1; s <= kcap; s++) {
-        const double a = t[kcap + dir * s], b = level ? k0 : t[kcap + dir * (s - 1)];
-        if (!(a - b <= D + (sbase + fabs(a) + fabs(b)) * 0x1p-40)) return (int)(s - 1);
-    }
-    return (int)kcap;
-}
-
 int choose_halo(lo_plan_t p, int a, int W)
 {
     if (p->d.window[a] > 0) W = p->d.window[a];
@@ -452,55 +441,6 @@ int choose_halo(lo_plan_t p, int a, int W)
     if (p->fast[a] && p->kind[a] == kKindTile)
         p->tile_rows[a] = p->tile_fix[a] > 0 ? p->tile_fix[a] : tile_len(p, a, H >= 40 || a == p->ndim - 1);
     return H;
-}
-
-// Windows of step n0 from the statistics of u in stats slot n0 (the same
-// bounds the last block of every step computes on the device), uploaded to the
-// step's window slot; halos sized from them.
-lo_status adapt_from_slot(lo_plan_t p, int64_t n0, hipStream_t s)
-{
-    std::vector<uint64_t> raw(kSlotStride);
-    HIPCHK(hipMemcpy(raw.data(), slot(p, n0), sizeof(uint64_t) * kSlotStride, hipMemcpyDeviceToHost));
-    double h[kSlotWords];
-    fold_slot(raw.data(), h);
-    const double M = h[6];
-    const double osc0 = h[7] + h[8];
-    int win[2 * kMaxDim] = {0, 0, 0, 0, 0, 0};
-    for (int a = 0; a < p->ndim; a++) {
-        int wp, wm;
-        if (p->d.window[a] > 0) {
-            wp = wm = p->d.window[a];
-        } else {
-            const double sbase = 1.0 + M + p->winp.slack_extra;
-            const double Dp = h[a] + p->dvf[a], Dm = h[3 + a] + p->dvb[a];
-            const double osc = osc0 + p->winp.osc_extra[a];
-            const int64_t kc = p->kcap[a];
-            wp = std::min(host_side(p->hkt[a], kc, 1, Dp, sbase, false), host_side(p->hkt[a], kc, 1, osc, sbase, true));
-            wm = std::min(host_side(p->hkt[a], kc, -1, Dm, sbase, false),
-                          host_side(p->hkt[a], kc, -1, osc, sbase, true));
-            if (p->winp.cap_err[a] && (wp >= kc || wm >= kc)) {
-                // the bound reached the table's end: the definition's minimisers may lie beyond it
-                const bool capp = host_side(p->hkt[a], kc, 1, Dp, sbase, false) >= kc &&
-                                  host_side(p->hkt[a], kc, 1, osc, sbase, true) >= kc;
-                const bool capm = host_side(p->hkt[a], kc, -1, Dm, sbase, false) >= kc &&
-                                  host_side(p->hkt[a], kc, -1, osc, sbase, true) >= kc;
-                if (capp || capm) p->hflags[0] |= kErrWindowCap;
-            }
-        }
-        win[2 * a] = wp;
-        win[2 * a + 1] = wm;
-        p->hflags[1 + a] = std::max(p->hflags[1 + a], (uint32_t)std::max(wp, wm));
-        p->halo[a] = choose_halo(p, a, std::max(wp, wm));
-        p->wseg[a] = std::max(wp, wm);
-    }
-    int* dst = p->win + (size_t)(((n0 % 2) + 2) % 2) * 2 * kMaxDim;
-    HIPCHK(hipMemcpyAsync(dst, win, sizeof(win), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (p->hflags[0] & kErrWindowCap) {
-        uint32_t e = p->hflags[0];
-        HIPCHK(hipMemcpy(p->flags, &e, sizeof(e), hipMemcpyHostToDevice));
-    }
-    return LO_OK;
 }
 
 // Halos from the widest window the kernels used since the last call.
@@ -599,14 +539,11 @@ lo_status prologue(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
     HIPCHK(launch_clear_slots(p->stats, p->nb, s));
     HIPCHK(launch_stats(u, p->ndim, p->n, slot(p, n0), p->nb, p->npts, (int64_t)kSlots * kSlotStride, s));
     for (int i = 0; i < 8; i++) p->hflags[i] = 0;
-    if (p->nb > 1) {
-        // every instance's first windows on the device, halos from their maximum
-        HIPCHK(launch_windows(p->winp, slot(p, n0), p->win + (size_t)(((n0 % 2) + 2) % 2) * 2 * kMaxDim, p->flags,
-                              p->nb, s));
-        return adapt_from_flags(p, s);
-    }
-    HIPCHK(hipStreamSynchronize(s));
-    return adapt_from_slot(p, n0, s);
+    // every instance's first windows on the device (the bounds the sweeps
+    // compute for the following steps), halos from their maximum
+    HIPCHK(launch_windows(p->winp, slot(p, n0), p->win + (size_t)(((n0 % 2) + 2) % 2) * 2 * kMaxDim, p->flags, p->nb,
+                          s));
+    return adapt_from_flags(p, s);
 }
 
 lo_status finish(lo_plan_t p, hipStream_t s, bool argmin)
@@ -858,6 +795,10 @@ lo_status lo_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, void* stre
     return finish(p, s, argmin != nullptr);
 }
 
+}  // extern "C"
+
+namespace {
+
 // An executable graph of kGraphSteps steps from phase n0 % 3 at the current halos.
 lo_status get_graph(lo_plan_t p, double* u, int64_t n0, hipGraphExec_t* out)
 {
@@ -895,19 +836,12 @@ lo_status get_graph(lo_plan_t p, double* u, int64_t n0, hipGraphExec_t* out)
     return LO_OK;
 }
 
-lo_status lo_run(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckpt_every, double* ckpt,
-                 void* stream)
+// The step loop of lo_run after its prologue.  It may return with segments
+// still running on s (the caller drains the stream on error).
+lo_status run_steps(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckpt_every, double* ckpt,
+                    hipStream_t s)
 {
-    if (!p || !u || nsteps < 0) return LO_ERR_INVALID;
-    if (ckpt && ckpt_every <= 0) return LO_ERR_INVALID;
-    hipStream_t s = (hipStream_t)stream;
     lo_status st = LO_OK;
-    if ((p->d.flags & LO_FLAG_AUTOTUNE) && !p->tuned) {
-        st = autotune(p, u, n0, s);
-        if (st) return st;
-    }
-    st = prologue(p, u, n0, s);
-    if (st) return st;
     const bool use_graph = graphable(p) && !ckpt;
     // From smooth data (u0 = 0, say) the windows first widen by several points
     // a step, more than the halos' slack covers over a whole segment.  While
@@ -950,6 +884,30 @@ lo_status lo_run(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckp
                 warm = grows ? next : 0;
             }
         }
+    }
+    return LO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lo_status lo_run(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckpt_every, double* ckpt,
+                 void* stream)
+{
+    if (!p || !u || nsteps < 0) return LO_ERR_INVALID;
+    if (ckpt && ckpt_every <= 0) return LO_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    lo_status st = LO_OK;
+    if ((p->d.flags & LO_FLAG_AUTOTUNE) && !p->tuned) {
+        st = autotune(p, u, n0, s);
+        if (st) return st;
+    }
+    st = prologue(p, u, n0, s);
+    if (!st) st = run_steps(p, u, n0, nsteps, ckpt_every, ckpt, s);
+    if (st) {
+        (void)hipStreamSynchronize(s);   // nothing of this call stays in flight
+        return st;
     }
     return finish(p, s, false);
 }

@@ -32,6 +32,16 @@ def test_library_exports_every_declared_symbol():
         assert name in _lib.SIGNATURES, name
 
 
+def test_library_exports_only_declared_c_symbols():
+    """Helpers stay internal: every unmangled function the library exports is
+    one the header declares."""
+    from paper_1210_4090_amd import _lib
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = {f[2] for f in (line.split() for line in out.stdout.splitlines())
+                if len(f) == 3 and f[1] == "T" and not f[2].startswith("_Z")}
+    assert exported == set(declared_functions())
+
+
 def test_status_strings():
     from paper_1210_4090_amd import _lib
     L = _lib.lib()
