@@ -962,15 +962,7 @@ lo_status lo_run_semigroup1(lo_plan_t p, double* u, int64_t nsteps, int32_t wind
         if (st) return st;
     }
     const double* hv = p->has_v ? p->dhv : nullptr;
-    if (hv) {
-        // prefix sums of the static tau V table, on the host in grid order
-        std::vector<double> h((size_t)N), q((size_t)N + 1);
-        HIPCHK(hipMemcpyAsync(h.data(), hv, sizeof(double) * (size_t)N, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        q[0] = 0.0;
-        for (int64_t i = 0; i < N; i++) q[(size_t)i + 1] = q[(size_t)i] + h[(size_t)i];
-        HIPCHK(hipMemcpyAsync(p->sg_q, q.data(), sizeof(double) * (size_t)(N + 1), hipMemcpyHostToDevice, s));
-    }
+    if (hv) HIPCHK(launch_prefix(hv, N, p->sg_q, s));   // prefix sums of the static tau V table
     HIPCHK(hipMemsetAsync(p->sg_sat, 0, sizeof(unsigned), s));
     for (int64_t k = 0; k < nsteps; k++) {
         HIPCHK(launch_semigroup1(u, p->dc_w, N, (int)W, p->dkt[0] + p->kcap[0], hv, p->sg_q, p->sg_sat, s));

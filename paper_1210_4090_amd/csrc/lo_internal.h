@@ -131,6 +131,8 @@ hipError_t launch_diff_range(const double* u, const double* snap, int64_t npts, 
 hipError_t launch_synth_hv(const double* basis, const double* coef_dev, int nmodes, int64_t npts,
                            double tau, double* hv, hipStream_t s);
 hipError_t launch_scale(const double* V, double tau, int64_t npts, double* hv, hipStream_t s);
+// Q[i] = hv[0] + ... + hv[i-1] for i in [0, N] (device, one block).
+hipError_t launch_prefix(const double* hv, int64_t N, double* Q, hipStream_t s);
 // One step of the first discrete semigroup (1-D): u -> w, Q the prefix sums of hv ([N + 1]).
 hipError_t launch_semigroup1(const double* u, double* w, int64_t N, int W, const double* kt_centre, const double* hv,
                              const double* Q, unsigned* sat, hipStream_t s);

@@ -19,6 +19,38 @@ namespace lo {
 namespace {
 
 constexpr int kSgBlock = 256;
+constexpr int kScanBlock = 1024;
+
+// Q[i] = hv[0] + ... + hv[i-1], i in [0, N], in one block: each thread sums a
+// contiguous run of hv, the run totals are scanned in order by thread 0, and
+// each thread then writes the prefixes of its run.
+__global__ __launch_bounds__(kScanBlock) void k_prefix(const double* __restrict__ hv, int64_t N,
+                                                       double* __restrict__ Q)
+{
+    __shared__ double part[kScanBlock];
+    const int t = (int)threadIdx.x;
+    const int64_t per = (N + kScanBlock - 1) / kScanBlock;
+    const int64_t b = min(N, (int64_t)t * per), e = min(N, b + per);
+    double sum = 0.0;
+    for (int64_t i = b; i < e; i++) sum += hv[i];
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        double acc = 0.0;
+        for (int i = 0; i < kScanBlock; i++) {
+            const double v = part[i];
+            part[i] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    double acc = part[t];
+    for (int64_t i = b; i < e; i++) {
+        Q[i] = acc;
+        acc += hv[i];
+    }
+    if (t == kScanBlock - 1) Q[N] = acc;   // the last run ends at N (it may be empty)
+}
 
 // Q[i] = hv[0] + ... + hv[i-1], i in [0, N]; lifted prefix P(i) = Q[i mod N] + floor(i / N) Q[N]
 __device__ __forceinline__ double lifted_prefix(const double* __restrict__ Q, int64_t i, int64_t N)
@@ -67,6 +99,12 @@ __global__ __launch_bounds__(kSgBlock) void k_semigroup1(const double* __restric
 }
 
 }  // namespace
+
+hipError_t launch_prefix(const double* hv, int64_t N, double* Q, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prefix, dim3(1), dim3(kScanBlock), 0, s, hv, N, Q);
+    return hipGetLastError();
+}
 
 hipError_t launch_semigroup1(const double* u, double* w, int64_t N, int W, const double* kt_centre, const double* hv,
                              const double* Q, unsigned* sat, hipStream_t s)
