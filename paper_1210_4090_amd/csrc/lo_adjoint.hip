@@ -266,59 +266,51 @@ hipError_t launch_project(const double* Lam, const double* basis, int M, int64_t
 
 namespace {
 
-// Largest |e| per axis over argmins laid out [steps][ndim][npts] (npts a
-// multiple of 8: 16-byte loads of 8 offsets of one axis).
-__global__ __launch_bounds__(kBlock) void k_absmax16(const int16_t* __restrict__ E, int64_t nchunks, int64_t npts,
-                                                     int ndim, uint32_t* __restrict__ out)
+// Largest |offset| of each axis in a record of int16 argmins laid out
+// [step][axis][npts].  Block x takes part x % G of segment (step, axis)
+// x / G; one global atomic a block.
+// V8: npts a multiple of 8, 16-byte loads of 8 offsets.
+template <bool V8>
+__global__ __launch_bounds__(kBlock) void k_absmax16(const int16_t* __restrict__ E, int64_t npts, int ndim, int G,
+                                                     uint32_t* __restrict__ out)
 {
-    uint32_t m[kMaxDim] = {0, 0, 0};
-    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nchunks; c += (int64_t)gridDim.x * kBlock) {
-        const int a = (int)(((c * 8) / npts) % ndim);
-        const int4 v = ((const int4*)E)[c];
-        const int w[4] = {v.x, v.y, v.z, v.w};
-        uint32_t mx = 0;
+    const int64_t seg = blockIdx.x / G;
+    const int part = (int)(blockIdx.x - seg * G);
+    const int a = (int)(seg % ndim);
+    const int16_t* base = E + seg * npts;
+    uint32_t mx = 0;
+    if (V8) {
+        const int4* b4 = (const int4*)base;
+        for (int64_t c = (int64_t)part * kBlock + threadIdx.x; c < npts / 8; c += (int64_t)G * kBlock) {
+            const int4 v = b4[c];
+            const int w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            mx = max(mx, (uint32_t)abs((int)(int16_t)(w[k] & 0xffff)));
-            mx = max(mx, (uint32_t)abs((int)(int16_t)((uint32_t)w[k] >> 16)));
+            for (int k = 0; k < 4; k++) {
+                mx = max(mx, (uint32_t)abs((int)(int16_t)(w[k] & 0xffff)));
+                mx = max(mx, (uint32_t)abs((int)(int16_t)((uint32_t)w[k] >> 16)));
+            }
         }
-        for (int b = 0; b < kMaxDim; b++)
-            if (b == a) m[b] = max(m[b], mx);
+    } else {
+        for (int64_t i = (int64_t)part * kBlock + threadIdx.x; i < npts; i += (int64_t)G * kBlock)
+            mx = max(mx, (uint32_t)abs((int)base[i]));
     }
-    for (int b = 0; b < ndim; b++) {
-        const uint32_t v = (uint32_t)wave_max((double)m[b]);
-        if (threadIdx.x % kWave == 0 && v) atomicMax(&out[b], v);
-    }
-}
-
-// The same, one offset at a time (any npts).
-__global__ __launch_bounds__(kBlock) void k_absmax16_any(const int16_t* __restrict__ E, int64_t total, int64_t npts,
-                                                         int ndim, uint32_t* __restrict__ out)
-{
-    uint32_t m[kMaxDim] = {0, 0, 0};
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
-        const int a = (int)((i / npts) % ndim);
-        const uint32_t v = (uint32_t)abs((int)E[i]);
-        for (int b = 0; b < kMaxDim; b++)
-            if (b == a) m[b] = max(m[b], v);
-    }
-    for (int b = 0; b < ndim; b++) {
-        const uint32_t v = (uint32_t)wave_max((double)m[b]);
-        if (threadIdx.x % kWave == 0 && v) atomicMax(&out[b], v);
-    }
+    block_atomic_max((int)mx, &out[a]);
 }
 
 }  // namespace
 
 hipError_t launch_absmax16(const int16_t* E, int64_t steps, int ndim, int64_t npts, uint32_t* out, hipStream_t s)
 {
-    const int64_t total = steps * ndim * npts;
-    if (total <= 0) return hipSuccess;
-    const int grid = 1024;
+    const int64_t nseg = steps * ndim;
+    if (nseg <= 0 || npts <= 0) return hipSuccess;
+    // about 2048 blocks in all, a part of one segment each
+    const int64_t per = (npts + 8 * kBlock - 1) / (8 * kBlock);   // blocks that a segment can keep busy
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(per, (2048 + nseg - 1) / nseg));
+    if (nseg * G > 0x7fffffff) return hipErrorInvalidValue;
     if (npts % 8 == 0)
-        hipLaunchKernelGGL(k_absmax16, dim3(grid), dim3(kBlock), 0, s, E, total / 8, npts, ndim, out);
+        hipLaunchKernelGGL(k_absmax16<true>, dim3((unsigned)(nseg * G)), dim3(kBlock), 0, s, E, npts, ndim, G, out);
     else
-        hipLaunchKernelGGL(k_absmax16_any, dim3(grid), dim3(kBlock), 0, s, E, total, npts, ndim, out);
+        hipLaunchKernelGGL(k_absmax16<false>, dim3((unsigned)(nseg * G)), dim3(kBlock), 0, s, E, npts, ndim, G, out);
     return hipGetLastError();
 }
 

@@ -119,6 +119,20 @@ __device__ __forceinline__ double wave_max_to63(double v)
     return v;
 }
 
+// Largest v >= 0 over the block into *dst with one global atomic (many
+// blocks contending on one address cost far more than a block's barrier).
+// Every thread of the block calls it.
+__device__ inline void block_atomic_max(int v, uint32_t* dst)
+{
+    __shared__ int s;
+    if (threadIdx.x == 0) s = 0;
+    __syncthreads();
+    v = (int)wave_max((double)v);
+    if (threadIdx.x % kWave == 0 && v > 0) atomicMax(&s, v);
+    __syncthreads();
+    if (threadIdx.x == 0 && s > 0) atomicMax(dst, (uint32_t)s);
+}
+
 // Block-wide max of five values, valid in thread 0 only (red: 40 doubles).
 __device__ inline void block_max5_to0(double& a, double& b, double& c, double& d, double& e, double* red)
 {

@@ -469,10 +469,7 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
         }
     }
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
-    if (ARG && a.argmin) {
-        amax = (int)wave_max((double)amax);
-        if (threadIdx.x % kWave == 0) atomicMax(&a.flags[4 + a.axis], (uint32_t)amax);
-    }
+    if (ARG && a.argmin) block_atomic_max(amax, &a.flags[4 + a.axis]);
     publish_stats<EPI>(st, a, red);
     maybe_next_windows(a);   // after this block's own work: off the critical path
 }
@@ -663,10 +660,7 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
         }
     }
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
-    if (ARG && a.argmin) {
-        amax = (int)wave_max((double)amax);
-        if (threadIdx.x % kWave == 0) atomicMax(&a.flags[4 + a.axis], (uint32_t)amax);
-    }
+    if (ARG && a.argmin) block_atomic_max(amax, &a.flags[4 + a.axis]);
     publish_stats<EPI>(st, a, red);
     maybe_next_windows(a);   // after this block's own work: off the critical path
 }
