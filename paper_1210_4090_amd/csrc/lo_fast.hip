@@ -712,12 +712,8 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
     } while (0)
 #define LO_CLAIM_LAUNCH_G(K, E, A, G)                                                                          \
     do {                                                                                                        \
-        if constexpr (A == 0) {                                                                                 \
-            if (wide) LO_CLAIM_LAUNCH_B(K, E, A, G, 2 * kBlock);                                                \
-            else LO_CLAIM_LAUNCH_B(K, E, A, G, kBlock);                                                         \
-        } else {                                                                                                \
-            LO_CLAIM_LAUNCH_B(K, E, A, G, kBlock);                                                              \
-        }                                                                                                       \
+        if (wide) LO_CLAIM_LAUNCH_B(K, E, A, G, 2 * kBlock);                                                    \
+        else LO_CLAIM_LAUNCH_B(K, E, A, G, kBlock);                                                             \
     } while (0)
 #define LO_CLAIM_LAUNCH(K, E, A)                                                                                \
     do {                                                                                                        \
@@ -779,18 +775,22 @@ hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double
     const int C = fast_tile_lines(a.g.nlines);
     const bool arg = a.argmin != nullptr;
     // A grid of few tiles (two blocks of 256 threads a CU or fewer) leaves the
-    // SIMDs short of waves: plain sweeps then take blocks of 512 threads (rows:
-    // 4 points a thread).  Argmin sweeps keep 256 (their two passes ran slower
-    // with 512).
+    // SIMDs short of waves: its sweeps then take blocks of 512 threads (rows:
+    // 4 points a thread), and tiles of 16 lines take 128 targets (twice the
+    // blocks, for a few more halo sources).
     const int64_t nr = a.kind == kKindRow ? std::max<int64_t>(1, 2048 / a.g.n) : 1;
-    const int64_t tiles = a.kind == kKindRow
-                              ? (a.g.nlines + nr - 1) / nr
-                              : ((a.g.n + a.tile_rows - 1) / a.tile_rows) * ((a.g.nlines + C - 1) / C);
-    const bool few = !arg && tiles * a.nb * 2 <= a.grid_cap;
+    int64_t tiles = a.kind == kKindRow
+                        ? (a.g.nlines + nr - 1) / nr
+                        : ((a.g.n + a.tile_rows - 1) / a.tile_rows) * ((a.g.nlines + C - 1) / C);
+    const bool few = tiles * a.nb * 2 <= a.grid_cap;
     const int row_ch = a.row_ch == 4 || (few && a.kind == kKindRow) ? 4 : 8;
     SweepArgs b = a;
     b.row_ch = row_ch;
-    const ClaimLds L = claim_layout(a.kind, a.g.n, a.tile_rows, a.halo, arg, row_ch, C);
+    if (few && a.kind == kKindTile && C == kTileLines && a.tile_rows > 128) {
+        b.tile_rows = 128;
+        tiles = ((a.g.n + 127) / 128) * ((a.g.nlines + C - 1) / C);
+    }
+    const ClaimLds L = claim_layout(a.kind, a.g.n, b.tile_rows, a.halo, arg, row_ch, C);
     // ROW: persistent blocks, about grid_cap in all (instances included), each
     // walking several tiles so that its fixed costs are amortised
     const int64_t cap = std::max(1, a.grid_cap / std::max(1, a.nb));
