@@ -175,6 +175,14 @@ void free_plan(lo_plan_t p)
     delete p;
 }
 
+// Waits for the stream when an entry point returns, on every path: nothing a
+// call launched is still running when it reports an error (its caller may
+// free the buffers at once).  On success the stream is already idle.
+struct StreamDrain {
+    hipStream_t s;
+    ~StreamDrain() { (void)hipStreamSynchronize(s); }
+};
+
 lo_status build_tables(lo_plan_t p)
 {
     for (int a = 0; a < p->ndim; a++) {
@@ -788,6 +796,7 @@ lo_status lo_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, void* stre
 {
     if (!p || !u) return LO_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
+    StreamDrain drain{s};
     lo_status st = prologue(p, u, n, s);
     if (st) return st;
     st = enqueue_step(p, u, n, argmin, s);
@@ -922,6 +931,7 @@ lo_status lo_run_decomp(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, doub
     if (W > p->kcap[0] || N + 2 * W > (int64_t)1 << 30) return LO_ERR_INVALID;
     if (p->time_dep && n0 + nsteps > p->ntcoef) return LO_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
+    StreamDrain drain{s};
     if (!p->dc_w) {
         lo_status st = alloc((void**)&p->dc_w, sizeof(double) * (size_t)N);
         if (!st) st = alloc((void**)&p->dc_cnt, sizeof(unsigned long long) * 2);
@@ -951,6 +961,7 @@ lo_status lo_run_semigroup1(lo_plan_t p, double* u, int64_t nsteps, int32_t wind
     const int64_t W = window > 0 ? window : p->kcap[0];
     if (W > p->kcap[0]) return LO_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
+    StreamDrain drain{s};
     if (!p->dc_w) {
         lo_status st = alloc((void**)&p->dc_w, sizeof(double) * (size_t)N);
         if (!st) st = alloc((void**)&p->dc_cnt, sizeof(unsigned long long) * 2);
@@ -999,6 +1010,7 @@ lo_status lo_time_kernels(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, do
 {
     if (!p || !u || !ms || nsteps <= 0) return LO_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
+    StreamDrain drain{s};
     lo_status st = prologue(p, u, n0, s);
     if (st) return st;
     // events around every sweep, and an empty pair each step whose interval
@@ -1227,6 +1239,7 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
     if (st) return st;
     if ((!ckpt && nsteps > 0) || ckpt_every <= 0) return LO_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
+    StreamDrain drain{s};
     st = backward_buffers(p, std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1)), grad_coef != nullptr);
     if (st) return st;
     const size_t bytes = sizeof(double) * (size_t)p->npts;
@@ -1272,6 +1285,7 @@ lo_status lo_run_record(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int1
 {
     if (!p || !u || nsteps < 0 || (!argmins && nsteps > 0)) return LO_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
+    StreamDrain drain{s};
     lo_status st = prologue(p, u, n0, s);
     for (int64_t k = 0; k < nsteps && !st; k++) {
         if (k > 0 && k % kGraphSteps == 0) st = adapt_from_flags(p, s);
@@ -1288,6 +1302,7 @@ lo_status lo_backward_recorded(lo_plan_t p, const int16_t* argmins, int64_t nste
     if (st) return st;
     if (!argmins && nsteps > 0) return LO_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
+    StreamDrain drain{s};
     st = backward_buffers(p, 1, grad_coef != nullptr);
     if (st) return st;
     const size_t bytes = sizeof(double) * (size_t)p->npts;
