@@ -82,8 +82,11 @@ struct lo_plan_s {
     double* bw_u = nullptr;          // recomputed state
     double* bw_lam[2] = {nullptr, nullptr};
     double* bw_Lam = nullptr;        // sum over steps of the adjoint of u^{n+1}
-    int16_t* bw_arg = nullptr;       // argmins of one segment [steps][ndim][npts]
-    int64_t bw_arg_steps = 0;
+    int16_t* bw_arg = nullptr;       // argmins of two segments [2][steps][ndim][npts]
+    int64_t bw_arg_steps = 0;        // steps of one of them
+    uint32_t* bw_err = nullptr;      // error bits of the reverse sweeps
+    hipStream_t bw_stream = nullptr; // lo_backward: segment recomputes, beside the reverse sweeps
+    hipEvent_t bw_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // start, recomputed[2], reversed[2]
     double* bw_part = nullptr;       // projection partial sums [nmodes][blocks] + [nmodes]
 };
 
@@ -164,6 +167,10 @@ void free_plan(lo_plan_t p)
         if (l) (void)hipFree(l);
     if (p->bw_Lam) (void)hipFree(p->bw_Lam);
     if (p->bw_arg) (void)hipFree(p->bw_arg);
+    if (p->bw_err) (void)hipFree(p->bw_err);
+    for (auto& e : p->bw_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (p->bw_stream) (void)hipStreamDestroy(p->bw_stream);
     if (p->bw_part) (void)hipFree(p->bw_part);
     if (p->dpofs) (void)hipFree(p->dpofs);
     if (p->dwinp) (void)hipFree(p->dwinp);
@@ -586,11 +593,12 @@ lo_status backward_buffers(lo_plan_t p, int64_t steps, bool coef)
     if (!st && coef && !p->bw_Lam) st = alloc((void**)&p->bw_Lam, bytes);
     if (!st && coef && !p->bw_part)
         st = alloc((void**)&p->bw_part, sizeof(double) * (size_t)p->nmodes * (project_blocks(p->npts) + 1));
+    if (!st && !p->bw_err) st = alloc((void**)&p->bw_err, sizeof(uint32_t));
     if (!st && steps > p->bw_arg_steps) {
         if (p->bw_arg) (void)hipFree(p->bw_arg);
         p->bw_arg = nullptr;
         p->bw_arg_steps = 0;
-        st = alloc((void**)&p->bw_arg, sizeof(int16_t) * (size_t)steps * p->ndim * p->npts);
+        st = alloc((void**)&p->bw_arg, sizeof(int16_t) * 2 * (size_t)steps * p->ndim * p->npts);
         if (!st) p->bw_arg_steps = steps;
     }
     return st;
@@ -1184,7 +1192,7 @@ lo_status reverse_steps(lo_plan_t p, const int16_t* E, int64_t n0, int64_t n1, c
         for (int a = p->ndim - 1; a >= 0; a--) {
             const int16_t* Ea = E + ((size_t)(n - n0) * p->ndim + a) * p->npts;
             double* Lam = (coef && a == p->ndim - 1) ? p->bw_Lam : nullptr;
-            HIPCHK(launch_scatter(Ea, p->bw_lam[*cur], p->bw_lam[*cur ^ 1], Lam, sa[a], p->flags, s));
+            HIPCHK(launch_scatter(Ea, p->bw_lam[*cur], p->bw_lam[*cur ^ 1], Lam, sa[a], p->bw_err, s));
             *cur ^= 1;
         }
     }
@@ -1207,9 +1215,10 @@ lo_status finish_backward(lo_plan_t p, int cur, double* grad_u0, double* grad_co
         for (int m = 0; m < p->nmodes; m++) grad_coef[m] = -p->d.tau * acc[m];
     }
     HIPCHK(hipStreamSynchronize(s));
-    uint32_t f0 = 0;
+    uint32_t f0 = 0, e0 = 0;
     HIPCHK(hipMemcpy(&f0, p->flags, sizeof(f0), hipMemcpyDeviceToHost));
-    errs |= f0;
+    HIPCHK(hipMemcpy(&e0, p->bw_err, sizeof(e0), hipMemcpyDeviceToHost));
+    errs |= f0 | e0;
     hf[0] = errs;
     for (int i = 0; i < 8; i++) p->hflags[i] = hf[i];
     p->have_diag = true;
@@ -1240,44 +1249,69 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
     if ((!ckpt && nsteps > 0) || ckpt_every <= 0) return LO_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
     StreamDrain drain{s};
-    st = backward_buffers(p, std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1)), grad_coef != nullptr);
+    const int64_t seg = std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1));
+    st = backward_buffers(p, seg, grad_coef != nullptr);
     if (st) return st;
+    if (!p->bw_stream) HIPCHK(hipStreamCreateWithFlags(&p->bw_stream, hipStreamNonBlocking));
+    for (auto& e : p->bw_ev)
+        if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipStream_t s2 = p->bw_stream;
+    StreamDrain drain2{s2};
     const size_t bytes = sizeof(double) * (size_t)p->npts;
+    const size_t seg_arg = (size_t)seg * p->ndim * p->npts;
     int cur = 0;
     HIPCHK(hipMemcpyAsync(p->bw_lam[cur], grad_uT, bytes, hipMemcpyDeviceToDevice, s));
     if (grad_coef) HIPCHK(hipMemsetAsync(p->bw_Lam, 0, bytes, s));
+    HIPCHK(hipMemsetAsync(p->bw_err, 0, sizeof(uint32_t), s));
+    // the recomputes run on s2, after everything the caller queued on s (the checkpoints)
+    HIPCHK(hipEventRecord(p->bw_ev[0], s));
+    HIPCHK(hipStreamWaitEvent(s2, p->bw_ev[0], 0));
     uint32_t hf[8] = {0};
     uint32_t errs = 0;
-    const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
-    for (int64_t k = nseg - 1; k >= 0 && !st; k--) {
+    ScatterArgs sa[2][kMaxDim];
+    // Segment k recomputed from its checkpoint (on s2) with every sweep's
+    // argmins in buffer k % 2; its largest offsets size its scatter tiles.
+    auto recompute = [&](int64_t k) -> lo_status {
         const int64_t n0 = k * ckpt_every, n1 = std::min(nsteps, n0 + ckpt_every);
-        if (k < nseg - 1) {   // errors of the previous segment's reverse sweeps, before the flags reset
-            uint32_t f0 = 0;
-            HIPCHK(hipMemcpyAsync(&f0, p->flags, sizeof(f0), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            errs |= f0;
+        int16_t* E = p->bw_arg + (size_t)(k % 2) * seg_arg;
+        HIPCHK(hipMemcpyAsync(p->bw_u, ckpt + (size_t)k * p->npts, bytes, hipMemcpyDeviceToDevice, s2));
+        lo_status r = prologue(p, p->bw_u, n0, s2);
+        for (int64_t n = n0; n < n1 && !r; n++) {
+            if (n > n0 && (n - n0) % kGraphSteps == 0) r = adapt_from_flags(p, s2);
+            if (!r) r = enqueue_step(p, p->bw_u, n, E + (size_t)(n - n0) * p->ndim * p->npts, s2);
         }
-        // recompute the segment from its checkpoint, keeping every sweep's argmins
-        HIPCHK(hipMemcpyAsync(p->bw_u, ckpt + (size_t)k * p->npts, bytes, hipMemcpyDeviceToDevice, s));
-        st = prologue(p, p->bw_u, n0, s);
-        for (int64_t n = n0; n < n1 && !st; n++) {
-            if (n > n0 && (n - n0) % kGraphSteps == 0) st = adapt_from_flags(p, s);
-            if (!st) st = enqueue_step(p, p->bw_u, n, p->bw_arg + (size_t)(n - n0) * p->ndim * p->npts, s);
-        }
-        if (st) break;
+        if (r) return r;
         uint32_t f[kFlagWords];
-        HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(f), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(f), hipMemcpyDeviceToHost, s2));
+        HIPCHK(hipStreamSynchronize(s2));
         errs |= f[0];
-        if (f[0] & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrArgRange)) break;
+        if (f[0] & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrArgRange)) return LO_ERR_WINDOW;
         for (int a = 0; a < p->ndim; a++) {
             hf[1 + a] = std::max(hf[1 + a], std::max(p->hflags[1 + a], fold_window(f, a)));
             hf[4 + a] = std::max(hf[4 + a], f[4 + a]);
         }
-        ScatterArgs sa[kMaxDim];
-        st = scatter_layouts(p, f + 4, sa);
-        if (!st) st = reverse_steps(p, p->bw_arg, n0, n1, sa, &cur, grad_coef != nullptr, s);
+        HIPCHK(hipEventRecord(p->bw_ev[1 + k % 2], s2));
+        return scatter_layouts(p, f + 4, sa[k % 2]);
+    };
+    // Segments are undone from the last.  The reverse sweeps of segment k (on
+    // s) run while segment k - 1 is recomputed (on s2) into the other buffer,
+    // which the reverse sweeps of segment k + 1 have released.
+    const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+    if (nseg > 0) st = recompute(nseg - 1);
+    for (int64_t k = nseg - 1; k >= 0 && !st; k--) {
+        const int64_t n0 = k * ckpt_every, n1 = std::min(nsteps, n0 + ckpt_every);
+        HIPCHK(hipStreamWaitEvent(s, p->bw_ev[1 + k % 2], 0));
+        st = reverse_steps(p, p->bw_arg + (size_t)(k % 2) * seg_arg, n0, n1, sa[k % 2], &cur, grad_coef != nullptr,
+                           s);
+        if (st) break;
+        HIPCHK(hipEventRecord(p->bw_ev[3 + k % 2], s));
+        if (k > 0) {
+            if (k + 1 < nseg) HIPCHK(hipStreamWaitEvent(s2, p->bw_ev[3 + (k + 1) % 2], 0));
+            st = recompute(k - 1);
+        }
     }
+    // a window or argmin error of a recompute is reported through errs
+    if (st == LO_ERR_WINDOW && (errs & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrArgRange))) st = LO_OK;
     return finish_backward(p, cur, grad_u0, grad_coef, errs, hf, st, s);
 }
 
@@ -1310,6 +1344,7 @@ lo_status lo_backward_recorded(lo_plan_t p, const int16_t* argmins, int64_t nste
     HIPCHK(hipMemcpyAsync(p->bw_lam[cur], grad_uT, bytes, hipMemcpyDeviceToDevice, s));
     if (grad_coef) HIPCHK(hipMemsetAsync(p->bw_Lam, 0, bytes, s));
     HIPCHK(hipMemsetAsync(p->flags, 0, sizeof(uint32_t) * kFlagWords, s));
+    HIPCHK(hipMemsetAsync(p->bw_err, 0, sizeof(uint32_t), s));
     // the largest offset of each axis sizes the scatter tiles' halos
     HIPCHK(launch_absmax16(argmins, nsteps, p->ndim, p->npts, p->flags + 4, s));
     uint32_t f[kFlagWords];
