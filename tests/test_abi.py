@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -92,3 +93,20 @@ def test_plan_rejects_bad_descriptors_without_touching_the_device():
     d.ndim = 4
     assert L.lo_plan(ctypes.byref(d), None, ctypes.byref(h)) == _lib.LO_ERR_INVALID
     assert L.lo_plan(None, None, ctypes.byref(h)) == _lib.LO_ERR_INVALID
+
+
+def test_missing_library_fails_loudly():
+    """Without the built HIP library the binding raises; there is no CPU
+    fallback (run in a child process so the loaded library is untouched)."""
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1210_4090_amd import _lib\n"
+        "_lib.LIB_PATH = '/nonexistent/liblo.so'\n"
+        "try:\n"
+        "    _lib.lib()\n"
+        "except RuntimeError as e:\n"
+        "    print('raised', 'missing' in str(e))\n"
+        "else:\n"
+        "    print('loaded')\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.stdout.strip() == "raised True", out.stdout + out.stderr
