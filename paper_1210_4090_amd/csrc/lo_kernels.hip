@@ -425,19 +425,31 @@ __global__ __launch_bounds__(kBlock) void k_stats(const double* __restrict__ u, 
     double am = 0.0, hi = -INFINITY, nlo = -INFINITY;
     const int64_t nn[3] = {n0, n1, n2};
     const int64_t st[3] = {1, n0, n0 * n1};
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npts;
-         x += (int64_t)gridDim.x * blockDim.x) {
+    // grid-stride walk over the points with the coordinates (i0, i1, i2) of x
+    // advanced by the stride's own coordinates (mixed-radix addition), so
+    // that no point needs a division
+    const int64_t G = (int64_t)gridDim.x * blockDim.x;
+    const int64_t g0 = G % n0, g1 = (G / n0) % n1, g2 = G / (n0 * n1);
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t c[3] = {x % n0, (x / n0) % n1, x / (n0 * n1)};
+    for (; x < npts; x += G) {
         const double v = u[x];
         am = fmax(am, fabs(v));
         hi = fmax(hi, v);
         nlo = fmax(nlo, -v);
         for (int ax = 0; ax < ndim; ax++) {
-            const int64_t i = (x / st[ax]) % nn[ax];
-            const int64_t y = (i == nn[ax] - 1) ? x - st[ax] * (nn[ax] - 1) : x + st[ax];
+            const int64_t y = (c[ax] == nn[ax] - 1) ? x - st[ax] * (nn[ax] - 1) : x + st[ax];
             const double d = u[y] - v;
             dp[ax] = fmax(dp[ax], d);
             dm[ax] = fmax(dm[ax], -d);
         }
+        c[0] += g0;
+        const int64_t k0 = c[0] >= n0 ? 1 : 0;
+        c[0] -= k0 * n0;
+        c[1] += g1 + k0;
+        const int64_t k1 = c[1] >= n1 ? 1 : 0;
+        c[1] -= k1 * n1;
+        c[2] += g2 + k1;
     }
     for (int ax = 0; ax < 3; ax++) {
         double t = 0.0;
@@ -612,7 +624,8 @@ hipError_t launch_stats(const double* u, int ndim, const int64_t* n, uint64_t* s
                         int64_t b_stats, hipStream_t s)
 {
     const int64_t n0 = n[0], n1 = ndim > 1 ? n[1] : 1, n2 = ndim > 2 ? n[2] : 1;
-    int g = grid_for(n0 * n1 * n2);
+    // a few hundred blocks: each folds its maxima into the slot with atomics
+    int g = std::min(grid_for(n0 * n1 * n2), 512);
     if (nb > 1) g = std::max(1, std::min(g, 8192 / nb));
     hipLaunchKernelGGL(k_stats, dim3(g, nb), dim3(kBlock), 0, s, u, ndim, n0, n1, n2, slot, b_u, b_stats);
     return hipGetLastError();
