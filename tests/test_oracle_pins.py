@@ -406,6 +406,12 @@ def test_semigroup1_without_potential_is_the_sweep(orc):
     w0, a0 = orc.sweep(u, 0, 0.05, 0.3)
     np.testing.assert_array_equal(w, w0)
     np.testing.assert_array_equal(a, a0)
+    # dyadic data with exact ties (see the tie-rule pins): same lowest offsets
+    u = np.random.default_rng(92).integers(-12, 13, 16) / 256.0
+    w, a = orc.semigroup1_step(u, 0.5, 0.25, None, with_argmin=True)
+    w0, a0 = orc.sweep(u, 0, 0.5, 0.25)
+    np.testing.assert_array_equal(w, w0)
+    np.testing.assert_array_equal(a, a0)
 
 
 def test_semigroup1_constant_potential(orc):
@@ -440,3 +446,122 @@ def test_semigroup1_order(orc):
     du = np.abs(wl.random_grid([N], 70))
     assert np.all(orc.semigroup1_step(u + du, tau, P, V) >= w)
     assert np.all(orc.semigroup1_step(u, tau, P, V + du) <= w)
+
+
+# ---- tie rule of the argmin (exact ties) ----------------------------------
+def _exact_sweep_1d(u, tau, P, R):
+    """Independent enumeration in exact rational arithmetic: for every target
+    i, the minimum over lifted offsets e in [-R, R] of u[(i+e) mod N] + k(-e),
+    k(s) = tau K*(s dx / tau) = (s dx)^2 / (2 tau) - P s dx (eq. HPV), and
+    the sorted list of every offset attaining it."""
+    from fractions import Fraction as F
+    N = len(u)
+    dx, t, p = F(1, N), F(tau), F(P)
+    out = []
+    for i in range(N):
+        vals = {}
+        for e in range(-R, R + 1):
+            d = F(-e) * dx
+            vals[e] = F(u[(i + e) % N]) + d * d / (2 * t) - p * d
+        m = min(vals.values())
+        out.append((m, sorted(e for e, v in vals.items() if v == m)))
+    return out
+
+
+@pytest.mark.parametrize("P", [0.0, 0.25, -0.375])
+def test_argmin_tie_rule_exact_ties(orc, P):
+    """Dyadic data (u on a 2^-8 grid, dx = 1/16, tau = 1/2, P a multiple of
+    1/128): every candidate sum is an exact multiple of 2^-8 in binary64, so
+    equal candidates are genuine ties, and they are frequent.  The reported offset must be the smallest lifted
+    offset among the exact minimisers (reading of the tie rule: lowest lifted
+    source), and the value the exact minimum.  Exact rational enumeration,
+    independent of the oracle's code."""
+    N, tau = 16, 0.5
+    rng = np.random.default_rng(91)
+    ties = 0
+    for rep in range(12):
+        u = rng.integers(-12, 13, N) / 256.0
+        w, arg = orc.sweep(u, 0, tau, P)
+        ref = _exact_sweep_1d(u, tau, P, R=4 * N)
+        for i, (m, es) in enumerate(ref):
+            assert w[i] == float(m), (rep, i, w[i], float(m))
+            assert arg[i] == es[0], (rep, i, arg[i], es)
+            ties += len(es) > 1
+    assert ties >= 12, ties   # the case is exercised, not vacuous
+
+
+def test_argmin_tie_rule_mirror_and_lift_ties(orc):
+    """Two ties fixed by symmetry, P = 0 (even cost):
+      * a spike u[i] = 1 on a zero line: target i is reached equally cheaply
+        from i - 1 and i + 1, so its offset is -1;
+      * N = 4 with only u[2] low: target 0 reaches residue 2 through the lifts
+        e = -2 and e = +2 at the same cost, so its offset is -2."""
+    N = 12
+    u = np.zeros(N)
+    u[5] = 1.0
+    w, arg = orc.sweep(u, 0, 0.5, 0.0)
+    assert arg[5] == -1 and w[5] == 0.5 * (1.0 / N) ** 2 / 0.5
+    assert np.all(arg[np.arange(N) != 5] == 0)
+    u = np.array([1.0, 1.0, 0.0, 1.0])
+    w, arg = orc.sweep(u, 0, 0.5, 0.0)
+    assert arg[0] == -2 and w[0] == 0.25
+    assert arg[2] == 0 and w[2] == 0.0
+
+
+# ---- first discrete semigroup against eq. cost1's straight-path action -----
+def _sg1_path_integrals(orc, N, tau, P, V, M=4.0):
+    """tau-weighted path averages I(y, x) of V that the oracle's first
+    semigroup charges, read off its output: with u = -M at one source y0 and
+    0 elsewhere, every target x takes a lift y of y0 as its minimiser (checked
+    through the argmin), and w[x] = fl(fl(-M + k(x - y)) - I(y, x)).
+    Returns (x, y, I) with y lifted."""
+    y0 = N // 3
+    u = np.zeros(N)
+    u[y0] = -M
+    w, arg = orc.semigroup1_step(u, tau, P, V, with_argmin=True)
+    xs = np.arange(N)
+    ys = xs + arg
+    assert np.all(np.mod(ys, N) == y0)
+    dx = 1.0 / N
+    k = orc.kinetic(xs - ys, dx, tau, P)
+    return xs, ys, (-M + k) - w
+
+
+def _straight_path_average(x, y, N, tau, Vf, Vint):
+    """tau times the mean of V over the straight path from y to x (lifted
+    grid indices), from the closed-form antiderivative: eq. cost1's potential
+    part, the path being traversed at constant speed in time tau."""
+    a, b = y / N, x / N
+    out = np.empty(len(x))
+    same = a == b
+    out[same] = tau * Vf(b[same])
+    d = ~same
+    out[d] = tau * (Vint(b[d]) - Vint(a[d])) / (b[d] - a[d])
+    return out
+
+
+def test_semigroup1_charges_the_straight_path_action(orc):
+    """Eq. cost1: the potential part of the cost of a move y -> x is tau times
+    the average of V along the straight path.  With V = cos 2 pi x +
+    0.3 sin 4 pi x (closed-form antiderivative), every charged I(y, x) must
+    equal that average within the trapezoid bound tau dx^2 max|V''| / 12
+    (plus rounding), and the error must fall at order 2 under refinement.  A
+    left-point or right-point rule misses the bound by an order of dx."""
+    tp = 2 * np.pi
+    Vf = lambda z: np.cos(tp * z) + 0.3 * np.sin(2 * tp * z)
+    Vint = lambda z: np.sin(tp * z) / tp - 0.3 * np.cos(2 * tp * z) / (2 * tp)
+    d2max = tp ** 2 + 0.3 * (2 * tp) ** 2
+    tau, P = 0.05, 0.3
+    errs = []
+    for N in (64, 128):
+        x = np.arange(N) / N
+        xs, ys, I = _sg1_path_integrals(orc, N, tau, P, Vf(x))
+        assert np.count_nonzero(xs != ys) >= N - 1 and np.max(np.abs(xs - ys)) >= 8
+        ref = _straight_path_average(xs, ys, N, tau, Vf, Vint)
+        err = np.abs(I - ref)
+        bound = tau * d2max / (12.0 * N * N) + 1e-13
+        assert np.all(err <= bound), (N, float(err.max()), bound)
+        assert np.all(err[xs == ys] <= 1e-15)           # no move: I = fl(tau V(x))
+        errs.append(float(err[xs != ys].max()))
+    order = np.log2(errs[0] / errs[1])
+    assert 1.7 < order < 2.3, (errs, order)
