@@ -26,8 +26,9 @@
  *    convex; displacements outside the table cost +inf).
  *  - Argmin offsets are e = source - target in cells along the axis, on the
  *    lifted line (so |e| may exceed n[a]/2); among equal minima the smallest
- *    e is reported.  They are int16: windows beyond +-32767 are rejected when
- *    argmins are requested.
+ *    e is reported.  They are int16: a call that requested argmins and met an
+ *    offset beyond +-32767 returns LO_ERR_UNSUPPORTED (its stored offsets are
+ *    then unusable).
  *  - Pointers documented "device" are HIP device memory owned by the caller;
  *    "host" pointers are read during the call only.  Streams are hipStream_t
  *    passed as void* (NULL = default stream).  A plan is used from one
@@ -83,7 +84,8 @@ typedef struct {
     int64_t kstar_half[3];
     int32_t window[3];         /* 0 = rigorous window computed on the device every step;
                                   > 0 = fixed half-width, swept by the exhaustive (brute) kernels
-                                  whatever the method (argmins at the edge raise LO_ERR_WINDOW) */
+                                  whatever the method (a minimiser on or past the edge
+                                  raises LO_ERR_WINDOW) */
     int32_t method;            /* lo_method */
     uint32_t flags;            /* LO_FLAG_* */
     double t0;                 /* time of step 0 */
@@ -171,9 +173,10 @@ lo_status lo_backward_recorded(lo_plan_t plan, const int16_t* argmins, int64_t n
 const char* lo_status_string(lo_status s);
 
 /* Diagnostics of the last lo_step/lo_run/lo_backward (host arrays [ndim],
- * each may be NULL): widest window used per axis, and the largest |argmin
- * offset| seen (only when argmins were produced, else -1). */
-lo_status lo_last_diag(lo_plan_t plan, int32_t* window_used, int32_t* max_abs_offset);
+ * each may be NULL): the largest |argmin offset| seen per axis (only when
+ * argmins were produced, else -1), and the widest window used.  Returns
+ * LO_ERR_WINDOW when that call's window saturated. */
+lo_status lo_last_diag(lo_plan_t plan, int32_t* max_abs_offset, int32_t* window_used);
 
 /* Copy the plan's kinetic cost for displacements s0 .. s0+count-1 of one
  * axis into a host array (for checking the table against an independent

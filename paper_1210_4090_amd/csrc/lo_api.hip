@@ -25,7 +25,8 @@ struct lo_plan_s {
     double dx[kMaxDim] = {0, 0, 0};
     int64_t kcap[kMaxDim] = {0, 0, 0};
     std::vector<double> hkt[kMaxDim];   // host kinetic tables, index s + kcap
-    double* dkt[kMaxDim] = {nullptr, nullptr, nullptr};
+    double* dkt[kMaxDim] = {nullptr, nullptr, nullptr};        // kinetic table, entry s = -kcap at dkt[a]
+    double* dkt_alloc[kMaxDim] = {nullptr, nullptr, nullptr};  // its allocation (+inf pads around a caller table)
     double kmaxabs[kMaxDim] = {0, 0, 0};
     double kzero_drop[kMaxDim] = {0, 0, 0};   // k(0) - min_s k(s), rounded up
     bool user_table[kMaxDim] = {false, false, false};
@@ -151,7 +152,7 @@ void free_plan(lo_plan_t p)
 {
     if (!p) return;
     for (int a = 0; a < kMaxDim; a++)
-        if (p->dkt[a]) (void)hipFree(p->dkt[a]);
+        if (p->dkt_alloc[a]) (void)hipFree(p->dkt_alloc[a]);
     if (p->dcoef) (void)hipFree(p->dcoef);
     if (p->dtcoef) (void)hipFree(p->dtcoef);
     if (p->dhv) (void)hipFree(p->dhv);
@@ -227,9 +228,18 @@ lo_status build_tables(lo_plan_t p)
         }
         p->kmaxabs[a] = mx;
         p->kzero_drop[a] = drop * (1.0 + 0x1p-40) + 0x1p-60;
-        lo_status st = alloc((void**)&p->dkt[a], sizeof(double) * t.size());
+        // A caller table is the cost's whole support (+inf beyond it), and a
+        // window may reach its end; the brute kernels' register-blocked loop
+        // reads up to kKinPad offsets past either side of the window, so the
+        // device copy carries kKinPad entries of +inf on each side.  (A
+        // mechanical table spans two periods, beyond every window and halo.)
+        const size_t pad = p->user_table[a] ? (size_t)kKinPad : 0;
+        std::vector<double> dev(t.size() + 2 * pad, INFINITY);
+        std::copy(t.begin(), t.end(), dev.begin() + pad);
+        lo_status st = alloc((void**)&p->dkt_alloc[a], sizeof(double) * dev.size());
         if (st) return st;
-        HIPCHK(hipMemcpy(p->dkt[a], t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice));
+        p->dkt[a] = p->dkt_alloc[a] + pad;
+        HIPCHK(hipMemcpy(p->dkt_alloc[a], dev.data(), sizeof(double) * dev.size(), hipMemcpyHostToDevice));
     }
     return LO_OK;
 }
@@ -993,7 +1003,7 @@ lo_status lo_run_semigroup1(lo_plan_t p, double* u, int64_t nsteps, int32_t wind
     return sat ? LO_ERR_WINDOW : LO_OK;
 }
 
-lo_status lo_last_diag(lo_plan_t p, int32_t* window_used, int32_t* max_abs_offset)
+lo_status lo_last_diag(lo_plan_t p, int32_t* max_abs_offset, int32_t* window_used)
 {
     if (!p || !p->have_diag) return LO_ERR_INVALID;
     for (int a = 0; a < p->ndim; a++) {

@@ -469,7 +469,10 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
         }
     }
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
-    if (ARG && a.argmin) block_atomic_max(amax, &a.flags[4 + a.axis]);
+    if (ARG && a.argmin) {
+        block_atomic_max(amax, &a.flags[4 + a.axis]);
+        if (amax > 32767) atomicOr(&a.flags[0], kErrArgRange);   // stored offsets wrapped: unusable
+    }
     publish_stats<EPI>(st, a, red);
     maybe_next_windows(a);   // after this block's own work: off the critical path
 }
@@ -660,7 +663,10 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
         }
     }
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
-    if (ARG && a.argmin) block_atomic_max(amax, &a.flags[4 + a.axis]);
+    if (ARG && a.argmin) {
+        block_atomic_max(amax, &a.flags[4 + a.axis]);
+        if (amax > 32767) atomicOr(&a.flags[0], kErrArgRange);   // stored offsets wrapped: unusable
+    }
     publish_stats<EPI>(st, a, red);
     maybe_next_windows(a);   // after this block's own work: off the critical path
 }

@@ -9,6 +9,7 @@
 namespace lo {
 
 constexpr int kMaxDim = 3;
+constexpr int kKinPad = 8;         // +inf entries on each side of a caller's kinetic table on the device
 constexpr int kSlots = 3;          // rotating stats slots: read n%3, write (n+1)%3, clear (n+2)%3
 constexpr int kSlotWords = 10;     // per slot: [a] max fwd diff, [3+a] max -fwd diff, [6] max|w|,
                                    // [7] max u, [8] max -u of the step result

@@ -63,7 +63,10 @@ __device__ __forceinline__ void take(double& best, int& arg, double v, int e)
 // superset of its window [-wp, wm]: the extra candidates are genuine lifted
 // sources, and none of them can tie the minimum (all minimisers lie inside
 // the window), so values and lowest offsets are those of the window.  The
-// costs depend only on (k, q), the same in every lane: scalar loads.
+// costs depend only on (k, q), the same in every lane: scalar loads.  They
+// are read for displacements -(TB-1+wm) .. TB-1+wp: a mechanical table spans
+// two periods (beyond any window that fits the LDS halo) and a caller's table
+// carries TB-1 entries of +inf past each end on the device.
 template <int ARG, int TB, class Off>
 __device__ __forceinline__ void blocked_loop(const double* lds, int lane, Off off, int wp, int wm,
                                              const double* __restrict__ kc, double (&best)[TB], int (&arg)[TB])
@@ -91,6 +94,7 @@ __device__ __forceinline__ void blocked_loop(const double* lds, int lane, Off of
 }
 
 constexpr int kTB = 8;          // consecutive targets per thread
+static_assert(kKinPad >= kTB - 1, "caller tables need TB - 1 entries of +inf past each end");
 constexpr int kTileC = 16;      // lines per tile (16 doubles = one 128-byte line)
 constexpr int kTileRP = kBlock / kTileC;
 constexpr int kTileR = kTileRP * kTB;   // real targets per tile: 128
@@ -209,7 +213,9 @@ __global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__
             if (ARG) {
                 const int e = A[t];
                 if (a.argmin) record_arg(a, idx, e, amax);
-                if (a.wfix > 0 && (e == -wp || e == wm)) atomicOr(&a.flags[0], kErrWindowEdge);
+                // a fixed window is not a proven bound: a minimiser on or beyond its edge
+                // (the blocked loop also offers offsets past it) leaves the result untrusted
+                if (a.wfix > 0 && (e <= -wp || e >= wm)) atomicOr(&a.flags[0], kErrWindowEdge);
             }
         }
         if (i0 + per_pass < N) {
@@ -355,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
             if (EPI) w = w - a.hv[idx];
             out[idx] = w;
             if (ARG && a.argmin) record_arg(a, idx, arg[k], amax);
-            if (ARG && a.wfix > 0 && (arg[k] == -wp || arg[k] == wm)) atomicOr(&a.flags[0], kErrWindowEdge);
+            if (ARG && a.wfix > 0 && (arg[k] <= -wp || arg[k] >= wm)) atomicOr(&a.flags[0], kErrWindowEdge);
         }
     }
     if (ARG && a.argmin) block_atomic_max(amax, &a.flags[4 + a.axis]);

@@ -168,7 +168,7 @@ class Plan:
     def diag(self):
         w = (ctypes.c_int32 * 3)()
         m = (ctypes.c_int32 * 3)()
-        st = lib().lo_last_diag(self._h, w, m)
+        st = lib().lo_last_diag(self._h, m, w)
         if st not in (_lib.LO_OK, _lib.LO_ERR_WINDOW):
             check("lo_last_diag", st)
         return list(w[: self.ndim]), list(m[: self.ndim])
