@@ -961,7 +961,7 @@ lo_status lo_run_decomp(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, doub
         if (p->time_dep)
             HIPCHK(launch_synth_hv(p->basis, p->dtcoef + n * p->nmodes, p->nmodes, p->npts, p->d.tau, p->dhv, s));
         HIPCHK(launch_decomp_step(u, p->dc_w, u, (int)N, (int)W, p->dkt[0] + p->kcap[0], eta * p->dx[0],
-                                  p->has_v ? p->dhv : nullptr, p->dc_cnt, s));
+                                  p->kmaxabs[0], p->has_v ? p->dhv : nullptr, p->dc_cnt, s));
     }
     unsigned long long c[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(c, p->dc_cnt, sizeof(c), hipMemcpyDeviceToHost, s));

@@ -138,8 +138,9 @@ hipError_t launch_prefix(const double* hv, int64_t N, double* Q, hipStream_t s);
 hipError_t launch_semigroup1(const double* u, double* w, int64_t N, int W, const double* kt_centre, const double* hv,
                              const double* Q, unsigned* sat, hipStream_t s);
 // One step of the decomposition comparison path (1-D): u -> w (sweep) -> u_out = w - hv.
+// tol: the slope tolerance on raw increments (eta dx); kabs: max |k| over the table.
 hipError_t launch_decomp_step(const double* u, double* w, double* u_out, int N, int W, const double* kt_centre,
-                              double tol, const double* hv, unsigned long long* counts, hipStream_t s);
+                              double tol, double kabs, const double* hv, unsigned long long* counts, hipStream_t s);
 hipError_t launch_potential_diffs(const double* V, int ndim, const int64_t* n, double* out6,
                                   hipStream_t s);
 hipError_t launch_sweep(int method, const double* in, double* out, const SweepArgs& a,
