@@ -228,6 +228,26 @@ lo_status lo_run_decomp(lo_plan_t plan, double* u, int64_t n0, int64_t nsteps, d
  * the plan on first use. */
 lo_status lo_run_semigroup1(lo_plan_t plan, double* u, int64_t nsteps, int32_t window, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lo_step
+ * without a plan, allocating nothing.  One step n (time t0 + n tau) in place on
+ * u (device [npts]) for the mechanical cost of desc (kstar_tab must be NULL:
+ * LO_ERR_UNSUPPORTED otherwise); tau_v: NULL (no potential) or device [npts]
+ * holding fl(tau V(t_n, x)), read only; argmin: NULL or device int16
+ * [ndim][npts] as in lo_step.  desc->flags is ignored.  Values and argmins
+ * equal lo_step's for the same descriptor and potential.
+ * Work memory: one static device array of about 34 MiB (kinetic tables, a
+ * second grid array of LO_NOALLOC_MAX_POINTS doubles, statistics, flags),
+ * which each GPU that runs this call holds until the process ends.  Grids of
+ * more than LO_NOALLOC_MAX_POINTS points return LO_ERR_UNSUPPORTED before any
+ * device work.  Every call on a GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other threads, other streams) race and must be
+ * serialised by the caller.  Runs on the current device; the stream must
+ * belong to it.  Synchronises on return; errors as lo_step. */
+#define LO_NOALLOC_MAX_POINTS 4194304
+lo_status lo_step_noalloc(const lo_desc* desc, const double* tau_v, double* u, int64_t n, int16_t* argmin,
+                          void* stream);
+
 #ifdef __cplusplus
 }
 #endif

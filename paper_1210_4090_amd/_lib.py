@@ -86,7 +86,10 @@ SIGNATURES = {
                                      ctypes.c_void_p]),
     "lo_backward_recorded": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                             ctypes.c_void_p, _f64p, ctypes.c_void_p]),
+    "lo_step_noalloc": (ctypes.c_int, [ctypes.POINTER(LoDesc), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
 }
+LO_NOALLOC_MAX_POINTS = 4194304
 
 
 def lib():

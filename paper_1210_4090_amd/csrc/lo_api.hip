@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -63,6 +64,7 @@ struct lo_plan_s {
     int* win = nullptr;          // windows of the current and next step: [2][2 * kMaxDim]
     WinParams winp;
     WinParams* dwinp = nullptr;  // device copy read by the sweeps that compute the next windows
+    bool next_win = true;        // the axis-0 sweep computes the next step's windows
     uint32_t* flags = nullptr;   // kFlagWords
     uint32_t hflags[8] = {0};    // folded: [0] errors, [1+a] window used, [4+a] max |argmin|
     bool have_diag = false;
@@ -543,7 +545,7 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.inv2c = 1.0 / (2.0 * A.cq);
         A.pofs = p->d.P[a] * p->d.tau / p->dx[a];
         A.kslack = 0x1p-40 * (1.0 + p->kmaxabs[a]);
-        if (a == 0) {
+        if (a == 0 && p->next_win) {
             // windows of step n + 1 from the statistics of u^n (slot n), one step early
             A.winp_dev = p->dwinp;
             A.win_slot = slot(p, n);
@@ -1369,3 +1371,146 @@ lo_status lo_backward_recorded(lo_plan_t p, const int16_t* argmins, int64_t nste
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// lo_step_noalloc: one step for callers that cannot allocate device memory.
+// Its work memory (kinetic tables, the second grid array the sweeps ping-pong
+// with, statistics slots, flags, windows) is one static device array, which
+// every GPU the library runs on holds until the process ends.  Host code never
+// passes the array's name to a kernel or a copy: on each device the array's
+// address comes from hipGetSymbolAddress, taken once with that device current.
+namespace {
+
+constexpr int64_t kNaTab = 65536 + 64;                 // doubles per axis table: 2 * 32767 + 1 costs
+constexpr int64_t kNaTabPad = 32;                      // and 32 unused doubles on either side
+constexpr int64_t kNaGrid = LO_NOALLOC_MAX_POINTS;     // the second grid array
+constexpr int64_t kNaStats = (int64_t)kSlots * kSlotStride;   // 64-bit words
+constexpr int64_t kNaFlags = 128;                      // doubles: 256 flag words >= kFlagWords
+constexpr int64_t kNaWin = 32;                         // doubles: 64 window ints >= 4 kMaxDim
+constexpr int64_t kNaOffGrid = kMaxDim * kNaTab;
+constexpr int64_t kNaOffStats = kNaOffGrid + kNaGrid;
+constexpr int64_t kNaOffFlags = kNaOffStats + kNaStats;
+constexpr int64_t kNaOffWin = kNaOffFlags + kNaFlags;
+constexpr int64_t kNaWords = kNaOffWin + kNaWin;
+static_assert(kNaOffGrid % 32 == 0 && kNaOffStats % 32 == 0 && kNaOffFlags % 32 == 0 && kNaOffWin % 32 == 0,
+              "every region starts on a 256-byte boundary");
+static_assert(2 * kNaFlags >= kFlagWords && 2 * kNaWin >= 4 * kMaxDim, "flag and window regions fit");
+
+static __device__ __align__(256) double scratch[kNaWords];
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mutex;
+double* g_na_base[kNaMaxDevices] = {};
+
+// The address of the current device's copy of `scratch`.
+lo_status noalloc_base(double** out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return LO_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_na_mutex);
+    if (!g_na_base[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return LO_ERR_HIP;
+        }
+        g_na_base[dev] = (double*)ptr;
+    }
+    *out = g_na_base[dev];
+    return LO_OK;
+}
+
+// max |k| and k(0) - min k of the mechanical cost over [-cap, cap] without the
+// table: k is a convex quadratic, so its extremes lie at the ends and next to
+// the vertex P tau / dx.
+void mech_extremes(int64_t cap, double dx, double tau, double P, double* maxabs, double* zero_drop)
+{
+    const double v = P * tau / dx;
+    double kmin = INFINITY, mx = 0.0;
+    auto visit = [&](int64_t s) {
+        if (s < -cap || s > cap) return;
+        const double k = mech_cost(s, dx, tau, P);
+        kmin = std::min(kmin, k);
+        mx = std::max(mx, fabs(k));
+    };
+    visit(-cap);
+    visit(cap);
+    if (std::isfinite(v) && fabs(v) < 4.0 * (double)cap) {
+        const int64_t c = (int64_t)floor(v);
+        for (int64_t s = c - 3; s <= c + 4; s++) visit(s);
+    }
+    if (kmin > mech_cost(0, dx, tau, P)) kmin = mech_cost(0, dx, tau, P);
+    *maxabs = mx;
+    *zero_drop = (mech_cost(0, dx, tau, P) - kmin) * (1.0 + 0x1p-40) + 0x1p-60;
+}
+
+}  // namespace
+
+extern "C" lo_status lo_step_noalloc(const lo_desc* desc, const double* tau_v, double* u, int64_t n,
+                                     int16_t* argmin, void* stream)
+{
+    // checks that need no device come first
+    if (!desc || !u) return LO_ERR_INVALID;
+    if (desc->ndim < 1 || desc->ndim > kMaxDim) return LO_ERR_INVALID;
+    if (!(desc->tau > 0) || !std::isfinite(desc->tau)) return LO_ERR_INVALID;
+    if (desc->method != LO_BRUTE && desc->method != LO_FAST) return LO_ERR_INVALID;
+    int64_t npts = 1;
+    for (int a = 0; a < desc->ndim; a++) {
+        if (desc->n[a] < 3 || desc->n[a] > kNaGrid) return LO_ERR_INVALID;
+        if (!(desc->period[a] > 0) || !std::isfinite(desc->period[a]) || !std::isfinite(desc->P[a]) ||
+            desc->window[a] < 0)
+            return LO_ERR_INVALID;
+        if (desc->kstar_tab[a]) return LO_ERR_UNSUPPORTED;
+        npts *= desc->n[a];
+        if (npts > kNaGrid) return LO_ERR_UNSUPPORTED;
+    }
+    double* base = nullptr;
+    lo_status st = noalloc_base(&base);
+    if (st) return st;
+
+    // a plan description on the host stack whose device pointers lie in the
+    // static array (its vectors stay empty: nothing is allocated)
+    lo_plan_s q;
+    lo_plan_t p = &q;
+    p->d = *desc;
+    p->ndim = desc->ndim;
+    p->npts = npts;
+    for (int a = 0; a < p->ndim; a++) {
+        p->n[a] = desc->n[a];
+        p->dx[a] = desc->period[a] / (double)desc->n[a];
+        p->kcap[a] = std::min<int64_t>(32767, std::max<int64_t>(64, 2 * p->n[a]));
+        if (desc->window[a] > p->kcap[a]) return LO_ERR_INVALID;
+        p->dkt[a] = base + a * kNaTab + kNaTabPad;
+        mech_extremes(p->kcap[a], p->dx[a], desc->tau, desc->P[a], &p->kmaxabs[a], &p->kzero_drop[a]);
+    }
+    p->scratch = base + kNaOffGrid;
+    p->stats = (uint64_t*)(base + kNaOffStats);
+    p->flags = (uint32_t*)(base + kNaOffFlags);
+    p->win = (int*)(base + kNaOffWin);
+    p->has_v = tau_v != nullptr;
+    p->dhv = const_cast<double*>(tau_v);   // read only
+    p->next_win = false;
+    choose_kernels(p);
+    fill_winparams(p);
+    // windows from the statistics of this step's own input: no potential step
+    // lies between them, so no potential margins
+    p->winp.lag = 0;
+    p->winp.hv_osc = 0.0;
+
+    hipStream_t s = (hipStream_t)stream;
+    StreamDrain drain{s};
+    for (int a = 0; a < p->ndim; a++)
+        HIPCHK(launch_mech_table(p->dkt[a], p->kcap[a], p->dx[a], desc->tau, desc->P[a], s));
+    HIPCHK(launch_fill_u32(p->flags, kFlagWords, 0u, s));
+    HIPCHK(launch_clear_slots(p->stats, 1, s));
+    HIPCHK(launch_stats(u, p->ndim, p->n, slot(p, n), 1, p->npts, kNaStats, s));
+    HIPCHK(launch_windows(p->winp, slot(p, n), p->win + (size_t)(((n % 2) + 2) % 2) * 2 * kMaxDim, p->flags, 1, s));
+    uint32_t f[kFlagWords];
+    HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(f), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int a = 0; a < p->ndim; a++) p->halo[a] = choose_halo(p, a, (int)fold_window(f, a));
+    st = enqueue_step(p, u, n, argmin, s);
+    if (st) return st;
+    return finish(p, s, argmin != nullptr);
+}

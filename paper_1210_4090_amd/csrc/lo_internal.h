@@ -126,6 +126,10 @@ hipError_t launch_windows(const WinParams& P, const uint64_t* slot, int* win_out
                           hipStream_t s);
 hipError_t launch_stats(const double* u, int ndim, const int64_t* n, uint64_t* slot, int nb, int64_t b_u,
                         int64_t b_stats, hipStream_t s);
+// t[s + cap] = the mechanical cost of s cells for s in [-cap, cap] (device-built, equal to the host's).
+hipError_t launch_mech_table(double* t, int64_t cap, double dx, double tau, double P, hipStream_t s);
+// w[0..n) = v (a kernel, so that no memset node enters a captured graph).
+hipError_t launch_fill_u32(uint32_t* w, int64_t n, uint32_t v, hipStream_t s);
 // per instance of a batch: [b][0] = enc max(u - snap), [b][1] = enc max(snap - u)
 hipError_t launch_diff_range(const double* u, const double* snap, int64_t npts, int nb, uint64_t* out,
                              hipStream_t s);

@@ -417,6 +417,30 @@ __global__ void k_clear_slots(uint64_t* stats)
     for (int i = threadIdx.x; i < kSlots * kSlotStride; i += blockDim.x) st[i] = enc_neg_inf();
 }
 
+// The mechanical cost tau K*(s dx / tau) = ((0.5 d) d) / tau - P d, d = s dx,
+// for s in [-cap, cap] at t[s + cap]: the host's evaluation order, every
+// operation rounded on its own (IEEE division, no contraction), so the table
+// equals the one a plan builds on the host bit for bit.
+__global__ __launch_bounds__(kBlock) void k_mech_table(double* __restrict__ t, int64_t cap, double dx, double tau,
+                                                       double P)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= 2 * cap;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double d = (double)(i - cap) * dx;
+        const double a = 0.5 * d;
+        const double b = a * d;
+        const double c = b / tau;
+        const double e = P * d;
+        t[i] = c - e;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ w, int64_t n, uint32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = v;
+}
+
 // Max forward / backward difference along every axis and max |u| of u.
 __global__ __launch_bounds__(kBlock) void k_stats(const double* __restrict__ u, int ndim, int64_t n0,
                                                   int64_t n1, int64_t n2, uint64_t* slot, int64_t b_u,
@@ -623,6 +647,18 @@ hipError_t launch_windows(const WinParams& P, const uint64_t* slot, int* win_out
 hipError_t launch_clear_slots(uint64_t* stats, int nb, hipStream_t s)
 {
     hipLaunchKernelGGL(k_clear_slots, dim3(nb), dim3(64), 0, s, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_mech_table(double* t, int64_t cap, double dx, double tau, double P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mech_table, dim3(grid_for(2 * cap + 1)), dim3(kBlock), 0, s, t, cap, dx, tau, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* w, int64_t n, uint32_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kBlock), 0, s, w, n, v);
     return hipGetLastError();
 }
 

@@ -234,6 +234,28 @@ class Plan:
         return out
 
 
+def step_noalloc(u: torch.Tensor, n: Sequence[int], tau: float, P: Sequence[float], tau_v=None, step: int = 0,
+                 period=None, method: str = "fast", window=None, t0: float = 0.0, argmin: bool = False,
+                 stream=None):
+    """One step in place on u without a plan and without device allocation
+    by the library (lo_step_noalloc): mechanical cost, tau_v = fl(tau V(t_n))
+    as a CUDA float64 tensor shaped like the grid, or None.  Returns the int16
+    argmins [ndim, *grid] if asked (allocated here, by torch)."""
+    shape = tuple(reversed([int(v) for v in n]))
+    _dev_f64(u, "u", shape)
+    if tau_v is not None:
+        _dev_f64(tau_v, "tau_v", shape)
+    desc = make_desc(n, tau, P, period, method, window, None, t0)
+    arg = None
+    if argmin:
+        arg = torch.empty((len(n),) + shape, dtype=torch.int16, device=u.device)
+    check("lo_step_noalloc", lib().lo_step_noalloc(
+        ctypes.byref(desc), ctypes.c_void_p(tau_v.data_ptr() if tau_v is not None else 0),
+        ctypes.c_void_p(u.data_ptr()), int(step), ctypes.c_void_p(arg.data_ptr() if arg is not None else 0),
+        _stream(stream)))
+    return arg
+
+
 def effective_H(sides: Sequence[int], P: np.ndarray, V_by_side: dict, tau: float, T: float,
                 method: str = "fast", stream=None) -> np.ndarray:
     """Batched discrete effective Hamiltonian of square 2-D instances

@@ -110,3 +110,23 @@ def test_missing_library_fails_loudly():
         "    print('loaded')\n" % ROOT)
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert out.stdout.strip() == "raised True", out.stdout + out.stderr
+
+
+def test_noalloc_step_refuses_before_device_work():
+    """lo_step_noalloc checks its descriptor before touching a device: a grid
+    beyond the static array, or a caller's kinetic table, is refused (this
+    runs without a GPU)."""
+    from paper_1210_4090_amd import _lib
+    from paper_1210_4090_amd.lo import make_desc
+    import numpy as np
+    L = _lib.lib()
+    big = make_desc([2048, 2049], 0.01, [0.0, 0.0])
+    st = L.lo_step_noalloc(ctypes.byref(big), None, ctypes.c_void_p(8), 0, None, None)
+    assert st == _lib.LO_ERR_UNSUPPORTED
+    keep = []
+    tab = make_desc([64], 0.01, [0.0], kstar_tabs=[np.linspace(1.0, 0.0, 9) ** 2], keep=keep)
+    st = L.lo_step_noalloc(ctypes.byref(tab), None, ctypes.c_void_p(8), 0, None, None)
+    assert st == _lib.LO_ERR_UNSUPPORTED
+    assert L.lo_step_noalloc(None, None, ctypes.c_void_p(8), 0, None, None) == _lib.LO_ERR_INVALID
+    small = make_desc([2], 0.01, [0.0])
+    assert L.lo_step_noalloc(ctypes.byref(small), None, ctypes.c_void_p(8), 0, None, None) == _lib.LO_ERR_INVALID
