@@ -165,14 +165,16 @@ def config1(n: int = 256, steps: int = 200) -> Workload:
     return Workload("1d_torus_n%d" % n, (n,), 0.05, (0.0,), steps, u0, V)
 
 
-def config2(n: int = 2048, steps: int = 1000, seed: int = 2) -> Workload:
+def config2(n: int = 2048, steps: int = 1000, seed: int = 2, n1: Optional[int] = None) -> Workload:
     """2-D torus, P = (0.3, 0.1), V = cos2pi x + cos2pi y + 0.5 cos2pi(x+y),
-    u0 = 8 seeded Fourier modes |k| <= 4 with amplitude 1/|k|^2, tau = 0.01."""
+    u0 = 8 seeded Fourier modes |k| <= 4 with amplitude 1/|k|^2, tau = 0.01.
+    The grid is n x n, or n points on axis 0 by n1 on axis 1."""
     rng = np.random.default_rng(seed)
     kv, amp, ph = random_modes(2, 8, 4.0, rng)
-    u0 = fourier_field([n, n], kv, amp, ph)
-    return Workload("2d_torus_%dx%d" % (n, n), (n, n), 0.01, (0.3, 0.1), steps, u0,
-                    _c2_potential([n, n]))
+    shape = [n, n if n1 is None else int(n1)]
+    u0 = fourier_field(shape, kv, amp, ph)
+    return Workload("2d_torus_%dx%d" % tuple(shape), tuple(shape), 0.01, (0.3, 0.1), steps, u0,
+                    _c2_potential(shape))
 
 
 def config3(n: int = 256, steps: int = 200, seed: int = 3) -> Workload:

@@ -327,9 +327,9 @@ def test_config3_full_size_first_steps(torch_dev, orc, method):
                                            ((2048, 1280), 0.01, (0.3, 0.1), 0.0)])
 def test_fast_argmins_attain_the_value(torch_dev, orc, n, tau, P, noise):
     """Fast-path argmins (in-place row sweeps included): values within 1e-12
-    of the oracle; every offset reproduces the returned value exactly from
-    the plan's cost table, and equals the oracle's offset wherever the two
-    values agree.  Small grids
+    of the oracle everywhere (at least 99% of them bit for bit); every offset
+    reproduces the returned value exactly from the plan's cost table, and
+    equals the oracle's offset wherever the two values agree.  Small grids
     run the launch shapes for few tiles (512-thread blocks); the 2048 x 1280
     grid has enough tiles on both axes for the 256-thread shapes."""
     torch = torch_dev
@@ -355,6 +355,10 @@ def test_fast_argmins_attain_the_value(torch_dev, orc, n, tau, P, noise):
         w = src + k[2 * N - e]
     assert np.array_equal(w - hv, got)
     same = got == ref
+    err = float(np.max(np.abs(got - ref)))
+    print("MEASURED fast argmins %s: %.4f%% of values bitwise, max |gpu - oracle| %.3g"
+          % (n, 100 * same.mean(), err), flush=True)
+    assert err <= FAST_TOL
     assert same.mean() > 0.99
     assert np.array_equal(arg[:, same], rarg[:, same].astype(np.int64))
 
