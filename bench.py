@@ -100,6 +100,39 @@ def measure_workload(torch, w, method, K, W, steps=None, autotune=False):
             "window_max": wins, "plan": plan, "V": V, "u0": u0}
 
 
+def brute_valu(torch, w, plan, V, u0):
+    """FP64 VALU work of the brute sweeps over one run: every step's windows
+    (read back after each step) give 2 (2 W + 1) lane operations per point and
+    axis (one add and one min per candidate)."""
+    u = u0.clone()
+    ops = 0.0
+    for n in range(w.steps):
+        plan.run(u, 1, n0=n)
+        wins, _ = plan.diag()
+        ops += sum(2.0 * (2 * W + 1) for W in wins) * w.npts
+    return ops
+
+
+def copy_ceiling(torch, mib=1024, reps=20):
+    """A plain device copy of `mib` MiB (read and write: twice the 256 MB
+    last-level cache), timed with HIP events: the practical HBM ceiling."""
+    n = mib * (1 << 20) // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return {"bytes_per_copy": 2 * n * 8, "us_per_copy": ms * 1e3, "GBs": 2 * n * 8 / (ms * 1e-3) / 1e9,
+            "how": "torch copy_ of %d MiB (read + write), mean of %d" % (mib, reps)}
+
+
 def measure_adjoint(torch, method, every=50, reps=2, autotune=False, record=False):
     """Differentiation workload (1024^2, 500 steps, 64 Fourier modes of V):
     forward with FP64 checkpoints every `every` steps, then the reverse pass
@@ -139,11 +172,11 @@ def measure_adjoint(torch, method, every=50, reps=2, autotune=False, record=Fals
             "nmodes": int(w.basis.shape[0])}
 
 
-def measure_hbar(torch, method, subset=32):
+def measure_hbar(torch, method, subset=None):
     """Batched effective Hamiltonians (512 instances, sides 256..1024,
-    tau = 0.02, T = 20): the batched library call over the whole set, and on
-    the first `subset` instances both the batched call and one plan per
-    instance run back to back."""
+    tau = 0.02, T = 20): the batched library call over the whole set, and
+    one plan per instance run back to back over the first `subset` instances
+    (all by default)."""
     import numpy as np
     from paper_1210_4090_amd import workloads as wl
     from paper_1210_4090_amd.lo import Plan, effective_H
@@ -161,10 +194,15 @@ def measure_hbar(torch, method, subset=32):
         return time.perf_counter() - t0
 
     all_idx = np.arange(bw.ninst)
+    subset = bw.ninst if subset is None else subset
     sub = all_idx[:subset]
-    batched(sub)                      # warm-up (code objects, allocator)
-    t_all = batched(all_idx)
-    t_sub = batched(sub)
+    batched(all_idx[:8])              # warm-up (code objects, allocator)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = effective_H(bw.sides, bw.P, Vd, bw.tau, bw.T, method=method)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    t_sub = t_all if subset == bw.ninst else batched(sub)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in sub:
@@ -181,13 +219,18 @@ def measure_hbar(torch, method, subset=32):
     # algorithmic bytes of every step of every instance: two sweeps of 16 B a
     # point and the tau V table (8 B a point), over the whole job's time
     step_bytes = float(sum(sweep_bytes(2, 1)))
+    width = out[:, 2] - out[:, 0]
+    vmax = np.array([bw.V_by_side[int(s)].max() for s in bw.sides])
     return {"instances": bw.ninst, "steps": steps, "total_points": float(pts.sum()),
+            "bracket_width": {"max": float(width.max()), "median": float(np.median(width)),
+                              "p90": float(np.quantile(width, 0.9)), "min": float(width.min())},
+            "max_abs_mid_minus_maxV": float(np.max(np.abs(out[:, 1] - vmax))),
             "batched_s": t_all, "hbar_per_s": bw.ninst / t_all,
             "updates_per_s": float(pts.sum()) * steps / t_all,
             "effective_GBs_whole_job": float(pts.sum()) * steps * step_bytes / t_all / 1e9,
             "hbm_frac_whole_job": float(pts.sum()) * steps * step_bytes / t_all / 1e9 / HBM_PEAK_GBS,
-            "subset": int(subset), "subset_batched_s": t_sub, "subset_one_plan_each_s": t_loop,
-            "subset_speedup_batched": t_loop / t_sub}
+            "per_instance_loop_instances": int(subset), "per_instance_loop_batched_s": t_sub,
+            "per_instance_loop_s": t_loop, "speedup_batched_vs_loop": t_loop / t_sub}
 
 
 # The paper's one timing (Section 5.1): the pendulum on 2^18 points to T = 8 in
@@ -266,20 +309,45 @@ def cpu_baseline(w, nsteps=30):
             % (nsteps, w.name, dt)}
 
 
-def _only_3d(torch, method):
+def _only_run(torch, w, method, steps):
+    """One run of `steps` steps of the workload from its u0 (for profiling)."""
+    from paper_1210_4090_amd.lo import Plan
+    V = torch.as_tensor(w.V, device="cuda")
+    plan = Plan(w.n, w.tau, w.P, V=V, method=method)
+    u = torch.as_tensor(w.u0, device="cuda").clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(u, steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": w.name, "steps": steps, "ms_per_run": dt * 1e3, "updates_per_s": w.npts * steps / dt}
+
+
+def _only_3d(torch, method, steps=None):
     from paper_1210_4090_amd import workloads as wl
-    m = measure_workload(torch, wl.config3(), method, 2, 1)
+    w = wl.config3()
+    if steps:
+        return _only_run(torch, w, method, steps)
+    m = measure_workload(torch, w, method, 2, 1)
     return {"updates_per_s": m["rate"], "ms_per_run": m["ms_per_run"], "kernel_ms": m["kernel_ms"],
             "all_axis_GBs": m["all_axis_GBs"]}
 
 
-# one secondary workload at a time (python bench.py --only NAME), for profiling runs
+def _only_2d(torch, method, steps=None):
+    from paper_1210_4090_amd import workloads as wl
+    w = wl.config2()
+    return _only_run(torch, w, method, steps or w.steps)
+
+
+# one secondary workload at a time (python bench.py --only NAME [--run-steps N]), for profiling runs
 ONLY = {
+    "2d": _only_2d,
     "3d": _only_3d,
-    "hbar": lambda torch, method: measure_hbar(torch, method),
-    "adjoint": lambda torch, method: measure_adjoint(torch, method, reps=1),
-    "adjoint_recorded": lambda torch, method: measure_adjoint(torch, method, reps=1, record=True),
-    "pendulum": lambda torch, method: measure_paper_pendulum(torch, method, reps=1),
+    "copy": lambda torch, method, steps=None: copy_ceiling(torch),
+    "hbar": lambda torch, method, steps=None: measure_hbar(torch, method),
+    "adjoint": lambda torch, method, steps=None: measure_adjoint(torch, method, reps=1),
+    "adjoint_recorded": lambda torch, method, steps=None: measure_adjoint(torch, method, reps=1, record=True),
+    "pendulum": lambda torch, method, steps=None: measure_paper_pendulum(torch, method, reps=1),
 }
 
 
@@ -292,8 +360,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--only", choices=sorted(ONLY), default=None,
-                    help="measure one secondary workload and print its figures (for profiling runs); no "
+                    help="measure one workload and print its figures (for profiling runs); no "
                          "headline line")
+    ap.add_argument("--run-steps", type=int, default=None,
+                    help="with --only 2d / 3d: one run of this many steps from u0")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -306,7 +376,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
     if args.only:
-        print(json.dumps({"workload": args.only, "figures": ONLY[args.only](torch, args.method)}), flush=True)
+        print(json.dumps({"workload": args.only, "figures": ONLY[args.only](torch, args.method, args.run_steps)}),
+              flush=True)
         return
     w = wl.config2()
     log("workload %s steps=%d method=%s K=%d W=%d" % (w.name, w.steps, args.method, args.steps, args.warmup))
@@ -315,6 +386,8 @@ def main():
         % (m["rate"], m["ms_per_run"], m["kernel_ms"], m["window_max"]))
     kname = FAST_2D_KERNELS.get(m["dominant_axis"]) if args.method == "fast" else None
     traffic = measured_traffic(kname)
+    ceil = copy_ceiling(torch)
+    log("copy ceiling: %.1f GB/s" % ceil["GBs"])
     out = {
         "metric": "grid-point min-plus updates/sec + HBM GB/s, plain vs batched H̄(P) vs fwd+adjoint",
         "value": m["rate"],
@@ -335,8 +408,12 @@ def main():
                      "frac": m["dominant_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "axis-%d sweep %s" % (m["dominant_axis"], kname or ""),
                      "algorithmic_bytes_per_launch": m["bytes_per_launch"],
-                     "kernel_ms": m["kernel_ms"]},
+                     "kernel_ms": m["kernel_ms"],
+                     "timing": "mean interval of a HIP event pair around each launch, on the plan's stream, "
+                               "over one full run (never below the kernel's own duration)",
+                     "copy_ceiling_GBs": ceil["GBs"], "frac_of_copy_ceiling": m["dominant_GBs"] / ceil["GBs"]},
         "effective_GBs_whole_step": sum(sweep_bytes(w.ndim, w.npts)) * w.steps / (m["ms_per_run"] * 1e-3) / 1e9,
+        "hbm_copy_ceiling": ceil,
     }
     if not args.no_extras:
         extras = {}
@@ -344,17 +421,27 @@ def main():
         mb = measure_workload(torch, w, other, 1, 0)
         extras["headline_workload_" + other] = {"updates_per_s": mb["rate"], "ms_per_run": mb["ms_per_run"],
                                                "kernel_ms": mb["kernel_ms"], "window_max": mb["window_max"]}
-        log("%s: %.4g updates/s" % (other, mb["rate"]))
-        del mb
+        bm = mb if other == "brute" else m
+        ops = brute_valu(torch, w, bm["plan"], bm["V"], bm["u0"])
+        extras["headline_workload_brute_valu"] = {
+            "lane_ops_per_run": ops, "ops_per_s": ops / (bm["ms_per_run"] * 1e-3),
+            "peak_ops_per_s": FP64_VALU_PEAK, "frac": ops / (bm["ms_per_run"] * 1e-3) / FP64_VALU_PEAK,
+            "count": "2 (2W + 1) FP64 add/min lane operations per point and axis, W each step's window"}
+        log("%s: %.4g updates/s; brute VALU %s" % (other, mb["rate"], extras["headline_workload_brute_valu"]))
+        del mb, bm
         w3 = wl.config3()
         m3 = measure_workload(torch, w3, args.method, 2, 1)
+        whole3 = sum(sweep_bytes(w3.ndim, w3.npts)) * w3.steps / (m3["ms_per_run"] * 1e-3) / 1e9
         extras["3d_torus_256^3_200steps"] = {
             "updates_per_s": m3["rate"], "ms_per_run": m3["ms_per_run"], "kernel_ms": m3["kernel_ms"],
             "all_axis_GBs": m3["all_axis_GBs"], "hbm_frac_dominant": m3["dominant_GBs"] / HBM_PEAK_GBS,
-            "window_max": m3["window_max"]}
+            "effective_GBs_whole_run": whole3, "hbm_frac_whole_run": whole3 / HBM_PEAK_GBS,
+            "frac_of_copy_ceiling_whole_run": whole3 / ceil["GBs"], "window_max": m3["window_max"]}
         log("3-D: %.4g updates/s, axis GB/s %s" % (m3["rate"], m3["all_axis_GBs"]))
         del m3
         extras["batched_hbar_512"] = measure_hbar(torch, args.method)
+        extras["batched_hbar_512"]["frac_of_copy_ceiling_whole_job"] = \
+            extras["batched_hbar_512"]["effective_GBs_whole_job"] / ceil["GBs"]
         log("batched hbar: %s" % extras["batched_hbar_512"])
         extras["fwd_adjoint_1024^2_500steps"] = measure_adjoint(torch, args.method)
         extras["fwd_adjoint_1024^2_500steps_recorded_argmins"] = measure_adjoint(torch, args.method, record=True)

@@ -184,10 +184,11 @@ lo_status lo_last_diag(lo_plan_t plan, int32_t* max_abs_offset, int32_t* window_
 lo_status lo_kinetic_table(lo_plan_t plan, int32_t axis, int64_t s0, int64_t count, double* out);
 
 /* Measurement aid: runs steps n0 .. n0+nsteps-1 on u (device [npts]) like
- * lo_run but without a graph, with HIP events on `stream` around every axis
- * sweep; ms (host [ndim]) receives the mean duration of each axis' kernel in
- * milliseconds, less the mean interval of an empty event pair recorded on the
- * same stream each step.  Synchronous. */
+ * lo_run but without a graph, with a pair of HIP events on `stream` around
+ * every axis sweep (the steps run back to back; the host reads the events
+ * every 30 steps); ms (host [ndim]) receives the mean interval of each axis'
+ * pair in milliseconds: the kernel's duration plus the events' own cost, so
+ * never less than a profiler's kernel duration.  Synchronous. */
 lo_status lo_time_kernels(lo_plan_t plan, double* u, int64_t n0, int64_t nsteps, double* ms, void* stream);
 
 /* Comparison path: the paper's own fast algorithm (Section 4) on a 1-D plan.

@@ -551,9 +551,11 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
             A.win_slot = slot(p, n);
             A.win_next = p->win + (size_t)((((n + 1) % 2) + 2) % 2) * 2 * kMaxDim;
         }
-        if (ev) HIPCHK(hipEventRecord(ev[2 * a], s));
+        if (ev) {
+            A.ev_start = ev[2 * a];
+            A.ev_stop = ev[2 * a + 1];
+        }
         HIPCHK(launch_sweep(p->d.method, in[a], out[a], A, s));
-        if (ev) HIPCHK(hipEventRecord(ev[2 * a + 1], s));
     }
     if (out[p->ndim - 1] != u)
         HIPCHK(hipMemcpyAsync(u, out[p->ndim - 1], sizeof(double) * p->npts * p->nb, hipMemcpyDeviceToDevice, s));
@@ -1033,36 +1035,32 @@ lo_status lo_time_kernels(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, do
     StreamDrain drain{s};
     lo_status st = prologue(p, u, n0, s);
     if (st) return st;
-    // events around every sweep, and an empty pair each step whose interval
-    // (the events' own cost) is subtracted from the sweeps'
-    hipEvent_t ev[2 * kMaxDim + 2];
-    const int nev = 2 * p->ndim + 2;
-    for (int i = 0; i < nev; i++) HIPCHK(hipEventCreate(&ev[i]));
-    double acc[kMaxDim] = {0, 0, 0}, empty = 0.0;
-    for (int64_t k = 0; k < nsteps && !st; k++) {
-        if (k > 0 && k % kGraphSteps == 0) {
-            st = adapt_from_flags(p, s);
-            if (st) break;
-        }
-        st = enqueue_step(p, u, n0 + k, nullptr, s, ev);
-        if (st) break;
-        if (hipEventRecord(ev[nev - 2], s) != hipSuccess || hipEventRecord(ev[nev - 1], s) != hipSuccess ||
-            hipEventSynchronize(ev[nev - 1]) != hipSuccess) {
-            st = LO_ERR_HIP;
-            break;
-        }
-        for (int a = 0; a < p->ndim; a++) {
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, ev[2 * a], ev[2 * a + 1]) != hipSuccess) st = LO_ERR_HIP;
-            acc[a] += t;
-        }
-        float t = 0.f;
-        if (hipEventElapsedTime(&t, ev[nev - 2], ev[nev - 1]) != hipSuccess) st = LO_ERR_HIP;
-        empty += t;
+    // a pair of events around every sweep of a segment of steps; the stream
+    // runs the segment's steps back to back and the host reads the intervals
+    // at the segment's end (where lo_run adapts its halos too)
+    constexpr int kSeg = kGraphSteps;
+    const int per = 2 * p->ndim;
+    std::vector<hipEvent_t> ev((size_t)kSeg * per, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) st = LO_ERR_HIP;
+    double acc[kMaxDim] = {0, 0, 0};
+    for (int64_t k0 = 0; k0 < nsteps && !st; k0 += kSeg) {
+        if (k0 > 0) st = adapt_from_flags(p, s);
+        const int64_t seg = std::min<int64_t>(kSeg, nsteps - k0);
+        for (int64_t k = 0; k < seg && !st; k++) st = enqueue_step(p, u, n0 + k0 + k, nullptr, s, &ev[k * per]);
+        if (!st && hipStreamSynchronize(s) != hipSuccess) st = LO_ERR_HIP;
+        for (int64_t k = 0; k < seg && !st; k++)
+            for (int a = 0; a < p->ndim; a++) {
+                float t = 0.f;
+                if (hipEventElapsedTime(&t, ev[k * per + 2 * a], ev[k * per + 2 * a + 1]) != hipSuccess)
+                    st = LO_ERR_HIP;
+                acc[a] += t;
+            }
     }
-    for (int i = 0; i < nev; i++) (void)hipEventDestroy(ev[i]);
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
     if (st) return st;
-    for (int a = 0; a < p->ndim; a++) ms[a] = std::max(0.0, (acc[a] - empty) / (double)nsteps);
+    for (int a = 0; a < p->ndim; a++) ms[a] = acc[a] / (double)nsteps;
     return finish(p, s, false);
 }
 

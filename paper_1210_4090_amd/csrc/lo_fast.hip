@@ -703,18 +703,18 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
 #define LO_CLAIM_LAUNCH_B(K, E, A, G, B)                                                                       \
     do {                                                                                                        \
         if (L.C == 1)                                                                                           \
-            hipLaunchKernelGGL((K<E, A, 1, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, in, out,      \
-                               a.kin.k, a, L, inv2c, pofs);                                                     \
+            LO_SWEEP_LAUNCH((K<E, A, 1, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, a, in, out,     \
+                            a.kin.k, a, L, inv2c, pofs);                                                        \
         else if constexpr (E == 1 && A == 0 && B == kBlock) {                                                   \
             if (a.tile_rows == kPfTile * (kBlock / kTileLines))                                                 \
-                hipLaunchKernelGGL((K<E, A, kTileLines, G, B, kPfTile>), dim3((unsigned)grid, a.nb), dim3(B),   \
-                                   lds, s, in, out, a.kin.k, a, L, inv2c, pofs);                                \
+                LO_SWEEP_LAUNCH((K<E, A, kTileLines, G, B, kPfTile>), dim3((unsigned)grid, a.nb), dim3(B),      \
+                                lds, s, a, in, out, a.kin.k, a, L, inv2c, pofs);                                \
             else                                                                                                \
-                hipLaunchKernelGGL((K<E, A, kTileLines, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, \
-                                   in, out, a.kin.k, a, L, inv2c, pofs);                                        \
+                LO_SWEEP_LAUNCH((K<E, A, kTileLines, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, a, \
+                                in, out, a.kin.k, a, L, inv2c, pofs);                                           \
         } else                                                                                                  \
-            hipLaunchKernelGGL((K<E, A, kTileLines, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, in,  \
-                               out, a.kin.k, a, L, inv2c, pofs);                                                \
+            LO_SWEEP_LAUNCH((K<E, A, kTileLines, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, a, in, \
+                            out, a.kin.k, a, L, inv2c, pofs);                                                   \
     } while (0)
 #define LO_CLAIM_LAUNCH_G(K, E, A, G)                                                                          \
     do {                                                                                                        \
@@ -727,8 +727,8 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
         else LO_CLAIM_LAUNCH_G(K, E, A, true);                                                                  \
     } while (0)
 #define LO_ROW_LAUNCH_G(E, A, CH, G)                                                                          \
-    hipLaunchKernelGGL((k_claim_row<E, A, CH, kRowPoints / CH, G>), dim3((unsigned)grid, a.nb),               \
-                       dim3(kRowPoints / CH), lds, s, in, out, a.kin.k, a, L, inv2c, pofs)
+    LO_SWEEP_LAUNCH((k_claim_row<E, A, CH, kRowPoints / CH, G>), dim3((unsigned)grid, a.nb),                  \
+                    dim3(kRowPoints / CH), lds, s, a, in, out, a.kin.k, a, L, inv2c, pofs)
 #define LO_ROW_LAUNCH_CH(E, A, CH)                                                                            \
     do {                                                                                                       \
         if (a.quad) LO_ROW_LAUNCH_G(E, A, CH, false);                                                          \

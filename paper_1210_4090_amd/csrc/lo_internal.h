@@ -1,6 +1,7 @@
 // Internal declarations shared by the host library and the gfx950 kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -115,7 +116,21 @@ struct SweepArgs {
     const WinParams* winp_dev;
     const uint64_t* win_slot;
     int* win_next;
+    // host side only: when set, the sweep's kernel is launched with these
+    // events recording its own start and end (lo_time_kernels)
+    hipEvent_t ev_start;
+    hipEvent_t ev_stop;
 };
+
+// Launch a sweep kernel K (parenthesised if it has template arguments) with
+// the SweepArgs A's timing events when it has them.
+#define LO_SWEEP_LAUNCH(K, G, B, SH, S, A, ...)                                              \
+    do {                                                                                      \
+        if ((A).ev_start)                                                                     \
+            hipExtLaunchKernelGGL(K, G, B, SH, S, (A).ev_start, (A).ev_stop, 0u, __VA_ARGS__); \
+        else                                                                                  \
+            hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                                  \
+    } while (0)
 
 constexpr int kKindRow = 0;     // whole lines in LDS, unit stride
 constexpr int kKindTile = 1;    // tile of lines x targets with a halo

@@ -599,8 +599,8 @@ hipError_t launch_row(const double* in, double* out, const SweepArgs& a, hipStre
     row_layout(a.g.n, a.halo, &nr, &RS, &H);
     const size_t lds = row_lds_bytes(a.g.n, a.halo);
     const int64_t G = (a.g.nlines + nr - 1) / nr;
-    hipLaunchKernelGGL((k_row_brute<ARG, EPI>), dim3((unsigned)G, a.nb), dim3(kBlock), lds, s, in, out, a.kin.k, a, H,
-                       nr, RS);
+    LO_SWEEP_LAUNCH((k_row_brute<ARG, EPI>), dim3((unsigned)G, a.nb), dim3(kBlock), lds, s, a, in, out, a.kin.k, a, H,
+                    nr, RS);
     return hipGetLastError();
 }
 
@@ -608,8 +608,8 @@ template <int ARG, int EPI>
 hipError_t launch_tile(const double* in, double* out, const SweepArgs& a, hipStream_t s)
 {
     const int64_t G = ((a.g.n + kTileR - 1) / kTileR) * ((a.g.nlines + kTileC - 1) / kTileC);
-    hipLaunchKernelGGL((k_tile_brute<ARG, EPI>), dim3((unsigned)G, a.nb), dim3(kBlock), tile_lds_bytes(a.halo), s, in,
-                       out, a.kin.k, a);
+    LO_SWEEP_LAUNCH((k_tile_brute<ARG, EPI>), dim3((unsigned)G, a.nb), dim3(kBlock), tile_lds_bytes(a.halo), s, a, in,
+                    out, a.kin.k, a);
     return hipGetLastError();
 }
 
