@@ -3,11 +3,13 @@
 // eq. uN, HIP graphs for it, diagnostics.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "lo_internal.h"
@@ -20,6 +22,7 @@ struct lo_plan_s {
     int grid_cap = 1024;         // blocks of a persistent sweep launch (4 per compute unit)
     std::vector<double> Pb;      // [nb][kMaxDim] rotation vector of each instance
     double* dpofs = nullptr;     // device [nb][kMaxDim] P tau / dx per instance (nb > 1)
+    double* dPb = nullptr;       // device [nb][kMaxDim] P per instance (nb > 1)
     int ndim = 0;
     int64_t n[kMaxDim] = {1, 1, 1};
     int64_t npts = 0;
@@ -176,6 +179,7 @@ void free_plan(lo_plan_t p)
     if (p->bw_stream) (void)hipStreamDestroy(p->bw_stream);
     if (p->bw_part) (void)hipFree(p->bw_part);
     if (p->dpofs) (void)hipFree(p->dpofs);
+    if (p->dPb) (void)hipFree(p->dPb);
     if (p->dwinp) (void)hipFree(p->dwinp);
     if (p->tune_u) (void)hipFree(p->tune_u);
     if (p->dc_w) (void)hipFree(p->dc_w);
@@ -437,7 +441,11 @@ void fill_winparams(lo_plan_t p)
         W.cap_err[a] = p->user_table[a] ? 0 : 1;
         W.wfix[a] = p->d.window[a];
         W.bk[a] = 2 * p->kcap[a] + 1;
+        W.dx[a] = p->dx[a];
+        W.P[a] = p->d.P[a];
     }
+    W.tau = p->d.tau;
+    W.P_b = p->nb > 1 ? p->dPb : nullptr;
     W.b_stats = (int64_t)kSlots * kSlotStride;
     W.b_win = 4 * kMaxDim;
     W.pofs_b = p->nb > 1 ? p->dpofs : nullptr;
@@ -546,10 +554,18 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.pofs = p->d.P[a] * p->d.tau / p->dx[a];
         A.kslack = 0x1p-40 * (1.0 + p->kmaxabs[a]);
         if (a == 0 && p->next_win) {
-            // windows of step n + 1 from the statistics of u^n (slot n), one step early
-            A.winp_dev = p->dwinp;
-            A.win_slot = slot(p, n);
-            A.win_next = p->win + (size_t)((((n + 1) % 2) + 2) % 2) * 2 * kMaxDim;
+            // windows of step n + 1 from the statistics of u^n (slot n), one step
+            // early: block 0 of the row and brute sweeps computes them after its
+            // own work; beside a fast tile sweep (which keeps its registers for
+            // the claims) a small kernel of their own does
+            int* next = p->win + (size_t)((((n + 1) % 2) + 2) % 2) * 2 * kMaxDim;
+            if (p->fast[0] && p->kind[0] == kKindTile && p->d.window[0] <= 0) {
+                HIPCHK(launch_windows(p->winp, slot(p, n), next, p->flags, p->nb, s));
+            } else {
+                A.winp_dev = p->dwinp;
+                A.win_slot = slot(p, n);
+                A.win_next = next;
+            }
         }
         if (ev) {
             A.ev_start = ev[2 * a];
@@ -618,13 +634,116 @@ lo_status backward_buffers(lo_plan_t p, int64_t steps, bool coef)
     return st;
 }
 
-// Launch-shape tuner (LO_FLAG_AUTOTUNE): time kTuneSteps steps of every
-// candidate shape on a copy of u and keep, per axis, the shape whose sweep
-// was fastest.  Every shape computes the same values (the minimum over a
-// target's claimants does not depend on how sources are grouped), so the
-// choice only affects speed.  The last axis keeps its 256-target tiles (its
-// sweep prefetches tau V for them).
+// Launch-shape tuner (LO_FLAG_AUTOTUNE).  The shapes: points per thread of a
+// row sweep (8, or 4 with blocks of twice the threads) and targets per tile of
+// a tile sweep (256 or 128).  Every shape computes the same values (the
+// minimum over a target's claimants does not depend on how sources are
+// grouped), so the choice only affects speed.
+//  - Steady state: the windows of the first steps of a run from smooth data
+//    are several times wider than later on, so the tuner first advances a copy
+//    of u by kTuneWarm steps with the default shapes, and times from there.
+//  - Both shapes of every axis are timed over kTuneSteps steps from that same
+//    state, each sweep's kernel between its own start and stop events; an axis
+//    leaves its default only for a gain of more than 2%.
+//  - Choices are kept per (grid, instances, method, sweep kinds, cost kinds)
+//    for the life of the process, and in the file named by LO_TUNE_CACHE when
+//    that is set (one choice a line, read once, appended); a plan whose key is
+//    known takes the choice without timing anything.
+constexpr int kTuneWarm = 60;
 constexpr int kTuneSteps = 8;
+
+lo_status run_steps(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckpt_every, double* ckpt,
+                    hipStream_t s);
+
+struct TuneChoice {
+    int row_ch[kMaxDim];
+    int tile_fix[kMaxDim];
+};
+
+std::mutex g_tune_mutex;
+std::vector<std::pair<std::string, TuneChoice>> g_tune_cache;
+bool g_tune_file_read = false;
+
+std::string tune_key(lo_plan_t p)
+{
+    char buf[256];
+    int k = snprintf(buf, sizeof(buf), "d%d nb%d m%d", p->ndim, p->nb, p->d.method);
+    for (int a = 0; a < p->ndim && k < (int)sizeof(buf); a++)
+        k += snprintf(buf + k, sizeof(buf) - k, " n%lld k%d q%d", (long long)p->n[a], p->kind[a],
+                      p->user_table[a] ? 0 : 1);
+    return std::string(buf);
+}
+
+// the cache file: lines "<key> | row_ch0 row_ch1 row_ch2 tile0 tile1 tile2"
+void tune_file_read()
+{
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char* path = getenv("LO_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (fgets(line, sizeof(line), f)) {
+        char* bar = strchr(line, '|');
+        if (!bar) continue;
+        std::string key(line, bar - line);
+        while (!key.empty() && key.back() == ' ') key.pop_back();
+        TuneChoice c;
+        if (sscanf(bar + 1, "%d %d %d %d %d %d", &c.row_ch[0], &c.row_ch[1], &c.row_ch[2], &c.tile_fix[0],
+                   &c.tile_fix[1], &c.tile_fix[2]) == 6)
+            g_tune_cache.emplace_back(key, c);
+    }
+    fclose(f);
+}
+
+void tune_file_append(const std::string& key, const TuneChoice& c)
+{
+    const char* path = getenv("LO_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s | %d %d %d %d %d %d\n", key.c_str(), c.row_ch[0], c.row_ch[1], c.row_ch[2], c.tile_fix[0],
+            c.tile_fix[1], c.tile_fix[2]);
+    fclose(f);
+}
+
+void apply_choice(lo_plan_t p, const TuneChoice& c)
+{
+    for (int a = 0; a < p->ndim; a++) {
+        p->row_ch[a] = c.row_ch[a];
+        p->tile_fix[a] = c.tile_fix[a];
+        if (p->kind[a] == kKindTile && c.tile_fix[a] > 0) p->tile_rows[a] = c.tile_fix[a];
+    }
+}
+
+// Time kTuneSteps steps of the current shapes from `from` (copied into tune_u
+// first); ms[a] receives each axis' summed kernel time.
+lo_status time_shapes(lo_plan_t p, const double* from, int64_t n0, double* ms, hipStream_t s)
+{
+    const size_t bytes = sizeof(double) * (size_t)p->npts * p->nb;
+    HIPCHK(hipMemcpyAsync(p->tune_u, from, bytes, hipMemcpyDeviceToDevice, s));
+    lo_status st = prologue(p, p->tune_u, n0, s);
+    if (st) return st;
+    std::vector<hipEvent_t> ev((size_t)kTuneSteps * 2 * p->ndim, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) st = LO_ERR_HIP;
+    for (int k = 0; k < kTuneSteps && !st; k++)
+        st = enqueue_step(p, p->tune_u, n0 + k, nullptr, s, &ev[(size_t)k * 2 * p->ndim]);
+    if (!st && hipStreamSynchronize(s) != hipSuccess) st = LO_ERR_HIP;
+    for (int a = 0; a < p->ndim; a++) ms[a] = 0.0;
+    for (int k = 1; k < kTuneSteps && !st; k++)   // the first step warms the shape up
+        for (int a = 0; a < p->ndim; a++) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[(size_t)k * 2 * p->ndim + 2 * a], ev[(size_t)k * 2 * p->ndim + 2 * a + 1]) !=
+                hipSuccess)
+                st = LO_ERR_HIP;
+            ms[a] += t;
+        }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return st;
+}
 
 lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
 {
@@ -632,53 +751,68 @@ lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
     bool any = false;
     for (int a = 0; a < p->ndim; a++) any |= p->fast[a];
     if (!any) return LO_OK;
+    const std::string key = tune_key(p);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        tune_file_read();
+        for (auto& e : g_tune_cache)
+            if (e.first == key) {
+                apply_choice(p, e.second);
+                return LO_OK;
+            }
+    }
     const size_t bytes = sizeof(double) * (size_t)p->npts * p->nb;
-    if (!p->tune_u) {
-        lo_status st = alloc((void**)&p->tune_u, bytes);
-        if (st) return st;
+    double* adv = nullptr;   // the steady state the shapes are timed from
+    lo_status st = alloc((void**)&adv, bytes);
+    if (!st && !p->tune_u) st = alloc((void**)&p->tune_u, bytes);
+    if (st) {
+        if (adv) (void)hipFree(adv);
+        return st;
     }
-    static const int kC[2] = {8, 4};
-    double ms[2][2][kMaxDim] = {};
-    hipEvent_t ev[2 * kMaxDim];
-    for (int i = 0; i < 2 * p->ndim; i++) HIPCHK(hipEventCreate(&ev[i]));
-    lo_status st = LO_OK;
-    for (int ci = 0; ci < 2 && !st; ci++) {
-        for (int ri = 0; ri < 2 && !st; ri++) {
-            for (int a = 0; a < p->ndim; a++) {
-                if (p->kind[a] == kKindTile) p->tile_fix[a] = tile_len(p, a, ri == 1 || a == p->ndim - 1);
-                else p->row_ch[a] = kC[ci];
-            }
-            if (hipMemcpyAsync(p->tune_u, u, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) st = LO_ERR_HIP;
-            if (!st) st = prologue(p, p->tune_u, n0, s);
-            for (int k = 0; k < kTuneSteps && !st; k++) {
-                st = enqueue_step(p, p->tune_u, n0 + k, nullptr, s, ev);
-                if (st) break;
-                if (hipEventSynchronize(ev[2 * p->ndim - 1]) != hipSuccess) st = LO_ERR_HIP;
-                for (int a = 0; a < p->ndim && !st && k > 0; a++) {   // step n0 warms up
-                    float t = 0.f;
-                    if (hipEventElapsedTime(&t, ev[2 * a], ev[2 * a + 1]) != hipSuccess) st = LO_ERR_HIP;
-                    ms[ci][ri][a] += t;
-                }
-            }
-        }
-    }
-    for (int i = 0; i < 2 * p->ndim; i++) (void)hipEventDestroy(ev[i]);
+    struct Free {
+        double* q;
+        ~Free() { (void)hipFree(q); }
+    } free_adv{adv};
+    HIPCHK(hipMemcpyAsync(adv, u, bytes, hipMemcpyDeviceToDevice, s));
+    st = prologue(p, adv, n0, s);
+    if (!st) st = run_steps(p, adv, n0, kTuneWarm, 0, nullptr, s);
+    if (!st) st = adapt_from_flags(p, s);
     if (st) return st;
-    for (int a = 0; a < p->ndim; a++) {
-        if (p->kind[a] == kKindTile) {
-            const double t128 = ms[0][0][a] + ms[1][0][a], t256 = ms[0][1][a] + ms[1][1][a];
-            p->tile_fix[a] = tile_len(p, a, t256 < t128 || a == p->ndim - 1);
-        } else {
-            const double c8 = ms[0][0][a] + ms[0][1][a], c4 = ms[1][0][a] + ms[1][1][a];
-            p->row_ch[a] = c4 < c8 ? 4 : 8;
+    const int64_t t0 = n0 + kTuneWarm;
+    TuneChoice def, alt, best;
+    for (int a = 0; a < kMaxDim; a++) {
+        def.row_ch[a] = 8;
+        alt.row_ch[a] = 4;
+        const bool wide = a < p->ndim && (p->halo[a] >= 40 || a == p->ndim - 1);
+        def.tile_fix[a] = a < p->ndim && p->kind[a] == kKindTile ? tile_len(p, a, wide) : 0;
+        alt.tile_fix[a] = a < p->ndim && p->kind[a] == kKindTile ? tile_len(p, a, !wide) : 0;
+    }
+    {
+        double ms_def[kMaxDim], ms_alt[kMaxDim];
+        apply_choice(p, def);
+        st = time_shapes(p, adv, t0, ms_def, s);
+        if (!st) {
+            apply_choice(p, alt);
+            st = time_shapes(p, adv, t0, ms_alt, s);
         }
+        if (st) return st;
+        best = def;
+        for (int a = 0; a < p->ndim; a++)
+            if (p->fast[a] && ms_alt[a] < 0.98 * ms_def[a]) {
+                best.row_ch[a] = alt.row_ch[a];
+                best.tile_fix[a] = alt.tile_fix[a];
+            }
+        apply_choice(p, best);
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        g_tune_cache.emplace_back(key, best);
+        tune_file_append(key, best);
     }
     // the run proper starts from its own prologue; captured steps used other shapes
     for (auto& g : p->graphs) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
         g = lo_plan_s::GraphEntry();
     }
-    return LO_OK;
+    return hipStreamSynchronize(s) == hipSuccess ? LO_OK : LO_ERR_HIP;
 }
 
 // A plan for nb instances that share the grid, time step and potential and
@@ -745,6 +879,9 @@ lo_status plan_create(const lo_desc* desc, const lo_potential* V, int nb, const 
                 po[(size_t)b * kMaxDim + a] = p->Pb[(size_t)b * kMaxDim + a] * p->d.tau / p->dx[a];
         st = alloc((void**)&p->dpofs, sizeof(double) * po.size());
         if (!st && hipMemcpy(p->dpofs, po.data(), sizeof(double) * po.size(), hipMemcpyHostToDevice) != hipSuccess)
+            st = LO_ERR_HIP;
+        if (!st) st = alloc((void**)&p->dPb, sizeof(double) * p->Pb.size());
+        if (!st && hipMemcpy(p->dPb, p->Pb.data(), sizeof(double) * p->Pb.size(), hipMemcpyHostToDevice) != hipSuccess)
             st = LO_ERR_HIP;
     }
     if (!st) st = setup_potential(p, V);

@@ -233,15 +233,18 @@ __device__ __forceinline__ int64_t remap_block(int64_t b, int64_t G)
 // runs it, probing 64 values of s at a time starting below `est` (a
 // closed-form guess for the mechanical cost; 0 when none): when the probe's
 // first value passes, everything below it passes too.  *cap is set when the
-// table ends before a failure.
-__device__ inline int window_side(const double* __restrict__ k, int64_t kcap, int dir, double D, double sbase,
-                                  bool level, int64_t est, bool* cap)
+// table ends before a failure.  kf(s) gives k(s): a table read, or the
+// mechanical cost evaluated in place (the same operations as the table's,
+// so the same values, without a memory round trip per probe).
+template <class KF>
+__device__ inline int window_side(KF kf, int64_t kcap, int dir, double D, double sbase, bool level, int64_t est,
+                                  bool* cap)
 {
     const int lane = threadIdx.x % kWave;
-    const double k0 = k[0];
+    const double k0 = kf(0);
     auto fails = [&](int64_t s) {
         if (s > kcap) return true;
-        const double a = k[dir * s], b = level ? k0 : k[dir * (s - 1)];
+        const double a = kf(dir * s), b = level ? k0 : kf(dir * (s - 1));
         const double d = a - b;
         const double lim = D + (sbase + fabs(a) + fabs(b)) * 0x1p-40;
         return !(d <= lim);
@@ -280,6 +283,19 @@ __device__ inline int window_side(const double* __restrict__ k, int64_t kcap, in
     return (int)kcap;
 }
 
+// The mechanical cost of s cells, tau K*(s dx / tau) for K(p) = (p + P)^2 / 2,
+// in the evaluation order of the plans' tables (each operation rounded on its
+// own, IEEE division).
+__device__ __forceinline__ double mech_cost_dev(int64_t s, double dx, double tau, double P)
+{
+    const double d = (double)s * dx;
+    const double a = 0.5 * d;
+    const double b = a * d;
+    const double c = b / tau;
+    const double e = P * d;
+    return c - e;
+}
+
 // Windows of every axis for the next step of instance `inst` (its kinetic
 // tables at inst * bk[a]), from the statistics in `slot` (recorded by the
 // step's sweep kernels, which have all completed).  Wave w of the block runs
@@ -294,16 +310,19 @@ __device__ inline void next_windows(const WinParams& P, int64_t inst, const uint
     const double M = stat_get(slot, 6) + (P.lag ? P.slack_extra : 0.0);
     const double osc0 = stat_get(slot, 7) + stat_get(slot, 8) + (P.lag ? P.hv_osc : 0.0);
     if (w < 4) {
+        const int dir = (w < 2) ? 1 : -1;
+        const bool level = (w & 1) != 0;
+        // every axis' statistic first, so that their loads overlap
+        double dst[kMaxDim] = {0.0, 0.0, 0.0};
+        if (!level)
+            for (int ax = 0; ax < P.ndim; ax++) dst[ax] = stat_get(slot, dir > 0 ? ax : 3 + ax);
         for (int ax = 0; ax < P.ndim; ax++) {
             if (P.wfix[ax] > 0) continue;
-            const int dir = (w < 2) ? 1 : -1;
-            const bool level = (w & 1) != 0;
             double D;
             if (level)
                 D = osc0 + P.osc_extra[ax];
             else
-                D = dir > 0 ? stat_get(slot, ax) + P.dvf[ax] * (P.lag ? 2.0 : 1.0)
-                            : stat_get(slot, 3 + ax) + P.dvb[ax] * (P.lag ? 2.0 : 1.0);
+                D = dst[ax] + (dir > 0 ? P.dvf[ax] : P.dvb[ax]) * (P.lag ? 2.0 : 1.0);
             const double sbase = 1.0 + M + P.slack_extra;
             int64_t est = 0;
             if (P.quad[ax]) {
@@ -317,7 +336,16 @@ __device__ inline void next_windows(const WinParams& P, int64_t inst, const uint
                 if (e > 0.0 && e < 1e9) est = (int64_t)e;
             }
             bool cap = false;
-            const int r = window_side(P.k[ax] + inst * P.bk[ax], P.kcap[ax], dir, D, sbase, level, est, &cap);
+            int r;
+            if (P.quad[ax]) {
+                const double dx = P.dx[ax], tau = P.tau;
+                const double Pa = P.P_b ? P.P_b[inst * kMaxDim + ax] : P.P[ax];
+                r = window_side([=](int64_t s) { return mech_cost_dev(s, dx, tau, Pa); }, P.kcap[ax], dir, D, sbase,
+                                level, est, &cap);
+            } else {
+                const double* __restrict__ kt = P.k[ax] + inst * P.bk[ax];
+                r = window_side([=](int64_t s) { return kt[s]; }, P.kcap[ax], dir, D, sbase, level, est, &cap);
+            }
             if (threadIdx.x % kWave == 0) {
                 part[ax][w] = r;
                 caps[ax][w] = cap ? 1 : 0;

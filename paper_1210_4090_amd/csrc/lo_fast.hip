@@ -668,7 +668,7 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
         if (amax > 32767) atomicOr(&a.flags[0], kErrArgRange);   // stored offsets wrapped: unusable
     }
     publish_stats<EPI>(st, a, red);
-    maybe_next_windows(a);   // after this block's own work: off the critical path
+    // (the next step's windows: a kernel of their own when axis 0 takes tiles)
 }
 
 ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg, int row_ch, int tile_lines)

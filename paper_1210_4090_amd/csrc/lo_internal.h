@@ -71,6 +71,11 @@ struct WinParams {
     // dvf / dvb, the oscillation by at most hv_osc, |w| by slack_extra
     int lag;
     double hv_osc;
+    // the mechanical cost evaluated in place by the search (quad axes)
+    double dx[kMaxDim];
+    double tau;
+    double P[kMaxDim];
+    const double* P_b;             // [nb][kMaxDim] per-instance P (nullptr: P[])
 };
 
 // Everything a sweep kernel needs besides the arrays.

@@ -65,8 +65,11 @@ class Plan:
     n: grid points per axis (axis 0 first).  V: static potential on the grid
     (CUDA float64 tensor shaped like the grid), or basis (CUDA tensor
     [M, *grid]) with static coef (M,) or time-dependent tcoef (steps, M).
-    autotune: the first run times the fast sweeps' launch shapes on a copy of
-    its input and keeps the fastest (results do not depend on the shape).
+    autotune: the first run advances a copy of its input past the first
+    steps and times the fast sweeps' launch shapes from there, keeping the
+    fastest per axis (results do not depend on the shape); the choice is kept
+    for the process's later plans of the same grid (and in the file named by
+    the environment variable LO_TUNE_CACHE, when set).
     """
 
     def __init__(self, n: Sequence[int], tau: float, P: Sequence[float], period=None,
@@ -257,16 +260,18 @@ def step_noalloc(u: torch.Tensor, n: Sequence[int], tau: float, P: Sequence[floa
 
 
 def effective_H(sides: Sequence[int], P: np.ndarray, V_by_side: dict, tau: float, T: float,
-                method: str = "fast", stream=None) -> np.ndarray:
+                method: str = "fast", autotune: bool = False, stream=None) -> np.ndarray:
     """Batched discrete effective Hamiltonian of square 2-D instances
     (lo_effective_H).  V_by_side: side -> CUDA float64 tensor [side, side].
-    Returns [ninst, 3] = (lower bound, midpoint, upper bound)."""
+    autotune: each batch's fast sweeps take the launch shapes the tuner picks
+    (results do not depend on them).  Returns [ninst, 3] = (lower bound,
+    midpoint, upper bound)."""
     ninst = len(sides)
     descs = (LoDesc * ninst)()
     pots = (LoPotential * ninst)()
     for i, s in enumerate(sides):
         s = int(s)
-        descs[i] = make_desc([s, s], tau, [float(P[i][0]), float(P[i][1])], method=method)
+        descs[i] = make_desc([s, s], tau, [float(P[i][0]), float(P[i][1])], method=method, autotune=autotune)
         V = _dev_f64(V_by_side[s], "V", (s, s))
         pots[i].table = V.data_ptr()
     out = np.zeros((ninst, 3), dtype=np.float64)

@@ -174,3 +174,15 @@ def test_full_batch_512_instances(torch_dev, orc):
     ref = _oracle_bracket(orc, 256, bw.P[i], bw.V_by_side[256], bw.tau, bw.T)
     print("instance", i, out[i], ref, out[i] - ref, flush=True)
     _fast_check("instance %d of the full batch" % i, out[i], ref)
+
+
+def test_autotuned_batches_bitwise_identical(torch_dev):
+    """The launch-shape tuner applied to every batch changes no bracket."""
+    torch = torch_dev
+    from paper_1210_4090_amd.lo import effective_H
+    bw = wl.config4(ninst_p1=3, ninst_p2=2, sides=(128, 192), tau=0.05, T=4.0, seed=14)
+    print_case("hbar autotuned")
+    Vd = _V_dev(torch, bw)
+    a = effective_H(bw.sides, bw.P, Vd, bw.tau, bw.T, method="fast")
+    b = effective_H(bw.sides, bw.P, Vd, bw.tau, bw.T, method="fast", autotune=True)
+    assert np.array_equal(a, b), a - b

@@ -5,10 +5,14 @@ argmin offsets); the fast path must agree within 1e-12 (max norm).  Inputs
 come from the seeded generators in paper_1210_4090_amd.workloads; no
 expected value comes from the GPU.
 """
+import os
+
 import numpy as np
 import pytest
 
 from paper_1210_4090_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.gpu
 
@@ -408,3 +412,34 @@ def test_fast_window_wider_than_the_staged_band(torch_dev, orc, n, amp, noise, a
         _check(u.cpu().numpy(), orc.run(u0, tau, P, 2, V=V), "fast")
     w, _ = p.diag()
     assert 511 < w[0] and (len(n) == 1 or w[0] + 1 < n[0]), w
+
+
+def test_autotune_choice_cached_in_a_file(tmp_path):
+    """LO_TUNE_CACHE: the first process tunes and appends its choice; a second
+    process with the same grid takes it from the file (nothing appended) and
+    computes the same values."""
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    out = tmp_path / "u%d.npy"
+    code = r'''
+import sys, numpy as np, torch
+sys.path.insert(0, %r)
+from paper_1210_4090_amd import workloads as wl
+from paper_1210_4090_amd.lo import Plan
+n = (384, 320)
+V = torch.as_tensor(wl.smooth_grid(list(n), 801), device="cuda")
+p = Plan(n, 0.02, (0.25, -0.15), V=V, method="fast", autotune=True)
+u = torch.as_tensor(wl.smooth_grid(list(n), 800), device="cuda")
+p.run(u, 90)
+np.save(sys.argv[1], u.cpu().numpy())
+''' % ROOT
+    env = dict(os.environ, LO_TUNE_CACHE=str(cache))
+    for i in (1, 2):
+        print_case("tune cache process", i)
+        r = subprocess.run([sys.executable, "-c", code, str(out) % i], env=env, capture_output=True, text=True,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        lines = cache.read_text().splitlines()
+        assert len(lines) == 1 and "|" in lines[0], lines
+    assert np.array_equal(np.load(str(out) % 1), np.load(str(out) % 2))
