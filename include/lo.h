@@ -71,11 +71,12 @@ typedef enum {
 #define LO_FLAG_AUTOTUNE 2u   /* LO_FAST: the first lo_run advances a copy of its input 60 steps
                                  (past the wide windows of the first steps), times each fast
                                  sweep's launch shapes (tile length, points per thread) over 8
-                                 steps from there and keeps, per axis, one more than 2% faster
-                                 than the default; the choice is kept for later plans of the same
-                                 grid in the process, and in the file named by the environment
-                                 variable LO_TUNE_CACHE when it is set.  Results do not depend on
-                                 the shape.  lo_effective_H applies it to each batch. */
+                                 steps from there (twice, alternately) and keeps, per axis, one
+                                 more than 3% faster than the default; the choice is kept for
+                                 later plans of the same grid in the process, and in the file
+                                 named by the environment variable LO_TUNE_CACHE when it is set.
+                                 Results do not depend on the shape.  lo_effective_H applies
+                                 it to each batch. */
 
 typedef struct {
     int32_t ndim;              /* 1..3 */

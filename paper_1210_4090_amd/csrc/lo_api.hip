@@ -555,11 +555,11 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.kslack = 0x1p-40 * (1.0 + p->kmaxabs[a]);
         if (a == 0 && p->next_win) {
             // windows of step n + 1 from the statistics of u^n (slot n), one step
-            // early: block 0 of the row and brute sweeps computes them after its
-            // own work; beside a fast tile sweep (which keeps its registers for
-            // the claims) a small kernel of their own does
+            // early: block 0 of the row, one-line tile and brute sweeps computes
+            // them after its own work; beside a fast sweep of 16-line tiles
+            // (which keeps its registers for the claims) a small kernel does
             int* next = p->win + (size_t)((((n + 1) % 2) + 2) % 2) * 2 * kMaxDim;
-            if (p->fast[0] && p->kind[0] == kKindTile && p->d.window[0] <= 0) {
+            if (p->fast[0] && p->kind[0] == kKindTile && p->d.window[0] <= 0 && tile_lines_of(p, 0) > 1) {
                 HIPCHK(launch_windows(p->winp, slot(p, n), next, p->flags, p->nb, s));
             } else {
                 A.winp_dev = p->dwinp;
@@ -643,8 +643,9 @@ lo_status backward_buffers(lo_plan_t p, int64_t steps, bool coef)
 //    are several times wider than later on, so the tuner first advances a copy
 //    of u by kTuneWarm steps with the default shapes, and times from there.
 //  - Both shapes of every axis are timed over kTuneSteps steps from that same
-//    state, each sweep's kernel between its own start and stop events; an axis
-//    leaves its default only for a gain of more than 2%.
+//    state, each sweep's kernel between its own start and stop events, twice
+//    and alternately (the faster of the two counts); an axis leaves its
+//    default only for a gain of more than 3%.
 //  - Choices are kept per (grid, instances, method, sweep kinds, cost kinds)
 //    for the life of the process, and in the file named by LO_TUNE_CACHE when
 //    that is set (one choice a line, read once, appended); a plan whose key is
@@ -788,17 +789,22 @@ lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
         alt.tile_fix[a] = a < p->ndim && p->kind[a] == kKindTile ? tile_len(p, a, !wide) : 0;
     }
     {
-        double ms_def[kMaxDim], ms_alt[kMaxDim];
-        apply_choice(p, def);
-        st = time_shapes(p, adv, t0, ms_def, s);
-        if (!st) {
+        // two rounds, alternating the shapes; the faster round of each counts
+        double ms_def[kMaxDim], ms_alt[kMaxDim], m[kMaxDim];
+        for (int a = 0; a < kMaxDim; a++) ms_def[a] = ms_alt[a] = INFINITY;
+        for (int round = 0; round < 2 && !st; round++) {
+            apply_choice(p, def);
+            st = time_shapes(p, adv, t0, m, s);
+            for (int a = 0; a < p->ndim && !st; a++) ms_def[a] = std::min(ms_def[a], m[a]);
+            if (st) break;
             apply_choice(p, alt);
-            st = time_shapes(p, adv, t0, ms_alt, s);
+            st = time_shapes(p, adv, t0, m, s);
+            for (int a = 0; a < p->ndim && !st; a++) ms_alt[a] = std::min(ms_alt[a], m[a]);
         }
         if (st) return st;
         best = def;
         for (int a = 0; a < p->ndim; a++)
-            if (p->fast[a] && ms_alt[a] < 0.98 * ms_def[a]) {
+            if (p->fast[a] && ms_alt[a] < 0.97 * ms_def[a]) {
                 best.row_ch[a] = alt.row_ch[a];
                 best.tile_fix[a] = alt.tile_fix[a];
             }

@@ -668,7 +668,11 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
         if (amax > 32767) atomicOr(&a.flags[0], kErrArgRange);   // stored offsets wrapped: unusable
     }
     publish_stats<EPI>(st, a, red);
-    // (the next step's windows: a kernel of their own when axis 0 takes tiles)
+    // the next step's windows: one-line tiles (an axis of fewer than 16 lines,
+    // 1-D grids) compute them here, after this block's own work; beside tiles
+    // of 16 lines a kernel of their own does (the search would cost every
+    // block of those registers)
+    if constexpr (C == 1) maybe_next_windows(a);
 }
 
 ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg, int row_ch, int tile_lines)
