@@ -33,6 +33,8 @@ struct lo_plan_s {
     double* dkt_alloc[kMaxDim] = {nullptr, nullptr, nullptr};  // its allocation (+inf pads around a caller table)
     double kmaxabs[kMaxDim] = {0, 0, 0};
     double kzero_drop[kMaxDim] = {0, 0, 0};   // k(0) - min_s k(s), rounded up
+    int kvert[kMaxDim] = {0, 0, 0};           // minimising offset of the table (instance 0)
+    int vabs[kMaxDim] = {0, 0, 0};            // largest |vertex| of the cost over the instances
     bool user_table[kMaxDim] = {false, false, false};
     int kind[kMaxDim] = {kKindRow, kKindTile, kKindTile};
     int halo[kMaxDim] = {0, 0, 0};       // halo of the next launches (adapted by lo_run)
@@ -225,13 +227,18 @@ lo_status build_tables(lo_plan_t p)
             if (!std::isfinite(t[i])) return LO_ERR_INVALID;
             mx = std::max(mx, fabs(t[i]));
         }
+        int vabs = 0;
         for (size_t b0 = 0; b0 < t.size(); b0 += len) {
             for (size_t i = b0 + 2; i < b0 + len; i++)
                 if (!((t[i] - t[i - 1]) >= (t[i - 1] - t[i - 2]))) return LO_ERR_INVALID;
             const double k0 = t[b0 + p->kcap[a]];
-            const double kmin = *std::min_element(t.begin() + b0, t.begin() + b0 + len);
-            drop = std::max(drop, k0 - kmin);
+            const auto mit = std::min_element(t.begin() + b0, t.begin() + b0 + len);
+            drop = std::max(drop, k0 - *mit);
+            const int v = (int)((mit - (t.begin() + b0)) - p->kcap[a]);
+            if (b0 == 0) p->kvert[a] = v;
+            vabs = std::max(vabs, std::abs(v));
         }
+        p->vabs[a] = vabs;
         p->kmaxabs[a] = mx;
         p->kzero_drop[a] = drop * (1.0 + 0x1p-40) + 0x1p-60;
         // A caller table is the cost's whole support (+inf beyond it), and a
@@ -475,6 +482,11 @@ int choose_halo(lo_plan_t p, int a, int W)
     // blocks load their tau V values before the claims
     if (p->fast[a] && p->kind[a] == kKindTile)
         p->tile_rows[a] = p->tile_fix[a] > 0 ? p->tile_fix[a] : tile_len(p, a, H >= 40 || a == p->ndim - 1);
+    // the fast sweeps stage a band of offsets centred on the cost's vertex
+    // (so that its loads need not wait for the window); the window lies
+    // within |vertex| + W of it
+    if (p->fast[a] && p->d.window[a] <= 0)
+        H = std::max(8, std::min((H + p->vabs[a] + 7) / 8 * 8, p->halo_max[a]));
     return H;
 }
 
@@ -553,6 +565,7 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.inv2c = 1.0 / (2.0 * A.cq);
         A.pofs = p->d.P[a] * p->d.tau / p->dx[a];
         A.kslack = 0x1p-40 * (1.0 + p->kmaxabs[a]);
+        A.kvert = p->kvert[a];
         if (a == 0 && p->next_win) {
             // windows of step n + 1 from the statistics of u^n (slot n), one step
             // early: block 0 of the row, one-line tile and brute sweeps computes
@@ -1624,6 +1637,8 @@ extern "C" lo_status lo_step_noalloc(const lo_desc* desc, const double* tau_v, d
         if (desc->window[a] > p->kcap[a]) return LO_ERR_INVALID;
         p->dkt[a] = base + a * kNaTab + kNaTabPad;
         mech_extremes(p->kcap[a], p->dx[a], desc->tau, desc->P[a], &p->kmaxabs[a], &p->kzero_drop[a]);
+        const double v = fabs(desc->P[a] * desc->tau / p->dx[a]);
+        p->vabs[a] = (int)std::min(v + 1.0, (double)p->kcap[a]);
     }
     p->scratch = base + kNaOffGrid;
     p->stats = (uint64_t*)(base + kNaOffStats);

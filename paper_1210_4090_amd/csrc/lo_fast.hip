@@ -256,28 +256,44 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
     double* W = KT + (2 * KH + 1);
     int* A = (int*)(W + L.RS);
 
+    // The cost band does not depend on the window (it is centred on the
+    // cost's vertex): its loads are issued before the window is read, so that
+    // the two latencies overlap.
+    // KT[i] = k(sb + i), i < 2 KH + 1: offsets [vertex - KH - g, vertex + KH - g]
+    // (a convex table's crossings also read k(smin - 1))
+    const int kcap = (int)min((int64_t)a.kin.kcap, (int64_t)0x7fffffff);
+    const int g = GEN ? 1 : 0;
+    const int vtx = GEN ? a.kvert : (int)floor(pofs + 0.5);
+    const int sb = vtx - KH - g;
+    constexpr int kKtRegs = (2 * 512 + 1 + BS - 1) / BS;   // the band has at most 2 * 512 + 1 entries
+    double ktv[kKtRegs];
+#pragma unroll
+    for (int j = 0; j < kKtRegs; j++) {
+        const int i = (int)threadIdx.x + j * BS;
+        const int s = sb + i;
+        ktv[j] = (i < 2 * KH + 1 && s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
+    }
+    const int64_t ntiles = (a.g.nlines + nr - 1) / nr;
+
     clear_slot(a.stats_clear);
     int wp = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis];
     int wm = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis + 1];
     wp = __builtin_amdgcn_readfirstlane(wp);
     wm = __builtin_amdgcn_readfirstlane(wm);
+#pragma unroll
+    for (int j = 0; j < kKtRegs; j++) {
+        const int i = (int)threadIdx.x + j * BS;
+        if (i < 2 * KH + 1) KT[i] = ktv[j];
+    }
     // the minimisers of the step lie within its window: claims are clipped to
     // t - p in [-wm - 1, wp + 1] (offsets beyond the table's end cost +inf and
     // never win)
-    const int kcap = (int)min((int64_t)a.kin.kcap, (int64_t)0x7fffffff);
     const int smin = max(-wm - 1, -kcap), smax = min(wp + 1, kcap);
-    // KT[i] = k(sb + i), i < 2 KH + 1: the window's band (a convex table's
-    // crossings also read k(smin - 1))
-    const int g = GEN ? 1 : 0, sb = smin - g;
-    for (int i = threadIdx.x; i < 2 * KH + 1; i += BS) {
-        const int s = sb + i;
-        KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
-    }
     // claims wrap once around the row (targets t of sources 0 .. N - 1 lie in
     // [smin, N - 1 + smax]); the main path needs the window inside the band
     const bool wraps = wp + 1 < N && wm + 1 < N;
-    const bool fast = wraps && smax - sb <= 2 * KH;
-    const double* K = KT - sb;   // K[s] = k(s), s in [sb, smax]
+    const bool fast = wraps && smin - g >= sb && smax <= sb + 2 * KH;
+    const double* K = KT - sb;   // K[s] = k(s), s in [sb, sb + 2 KH]
     const double gsl = a.kslack;
     const int kbase = r * N;
     auto key = [N, kbase](int t) { return skc<CH>(kbase + (t < 0 ? t + N : (t >= N ? t - N : t))); };
@@ -285,7 +301,6 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
     SweepStats st;
     int amax = 0;
     bool bad = false;
-    const int64_t ntiles = (a.g.nlines + nr - 1) / nr;
     // outputs, argmins and statistics of one tile row from the keys
     auto emit = [&](int64_t row, bool ok) {
         if (!ok) return;
@@ -388,6 +403,8 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
                     uu[2 + 2 * k] = v.y;
                 }
                 uu[CH + 1] = src[p0 + CH == N ? 0 : p0 + CH];
+            }
+            if (ok) {
 #pragma unroll
                 for (int k = 0; k < CH; k++) {
                     W[gs + k] = INFINITY;
@@ -524,32 +541,25 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
     double* W = KT + (2 * KH + 1);
     int* A = (int*)(W + (size_t)L.NT * kKeyStride);
 
-    clear_slot(a.stats_clear);
-    int wp = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis];
-    int wm = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis + 1];
-    wp = __builtin_amdgcn_readfirstlane(wp);
-    wm = __builtin_amdgcn_readfirstlane(wm);
-
-    // offsets beyond the table's end cost +inf and never win
+    // The loads that the window does not decide are issued before the window
+    // is read, so that their latencies overlap: the cost band (centred on the
+    // cost's vertex) and the tau V values of this thread's outputs.
+    // KT[i] = k(sb + i), i < 2 KH + 1: offsets [vertex - KH - g, vertex + KH - g]
+    // (a convex table's crossings also read k(smin - 1))
     const int kcap = (int)min((int64_t)a.kin.kcap, (int64_t)0x7fffffff);
-    const int smin = max(-wm - 1, -kcap), smax = min(wp + 1, kcap);
-    // KT[i] = k(sb + i), i < 2 KH + 1: the window's band (a convex table's
-    // crossings also read k(smin - 1))
-    const int g = GEN ? 1 : 0, sb = smin - g;
-    for (int i = threadIdx.x; i < 2 * KH + 1; i += BS) {
+    const int g = GEN ? 1 : 0;
+    const int vtx = GEN ? a.kvert : (int)floor(pofs + 0.5);
+    const int sb = vtx - KH - g;
+    constexpr int kKtRegs = (2 * 512 + 1 + BS - 1) / BS;   // the band has at most 2 * 512 + 1 entries
+    double ktv[kKtRegs];
+#pragma unroll
+    for (int j = 0; j < kKtRegs; j++) {
+        const int i = (int)threadIdx.x + j * BS;
         const int s = sb + i;
-        KT[i] = (s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
-    }
-    const bool fast = smax - sb <= 2 * KH;
-    const double* K = KT - sb;   // K[s] = k(s), s in [sb, smax]
-    const double gsl = a.kslack;
-    for (int t = q; t < NT; t += BS / C) {
-        W[t * kKeyStride + c] = INFINITY;
-        if (ARG) A[t * kKeyStride + c] = 0x7fffffff;
+        ktv[j] = (i < 2 * KH + 1 && s >= -kcap && s <= kcap) ? kc[s] : INFINITY;
     }
     // PF > 0 (potential step, tiles of PF (BS / C) targets): the tau V values
-    // of this thread's outputs are loaded now, so that their latency passes
-    // during the claims
+    // of this thread's outputs, whose latency then passes during the claims
     double hvp[PF > 0 ? PF : 1];
     if (PF > 0 && lok) {
         const double* __restrict__ h = a.hv + lbase + (int64_t)S * r0;
@@ -559,9 +569,38 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
             hvp[i] = t < Rt ? h[(int64_t)S * t] : 0.0;
         }
     }
+    const double* __restrict__ src = in + lbase;
+    auto load_chunk = [&](int p0, double (&uu)[kCh + 2]) {
+        int r = (p0 - 1) % N;
+        if (r < 0) r += N;
+#pragma unroll
+        for (int k = 0; k < kCh + 2; k++) {
+            uu[k] = src[S * r];
+            r = r + 1 == N ? 0 : r + 1;
+        }
+    };
+
+    clear_slot(a.stats_clear);
+    int wp = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis];
+    int wm = a.wfix > 0 ? a.wfix : a.win_in[2 * a.axis + 1];
+    wp = __builtin_amdgcn_readfirstlane(wp);
+    wm = __builtin_amdgcn_readfirstlane(wm);
+    for (int t = q; t < NT; t += BS / C) {
+        W[t * kKeyStride + c] = INFINITY;
+        if (ARG) A[t * kKeyStride + c] = 0x7fffffff;
+    }
+#pragma unroll
+    for (int j = 0; j < kKtRegs; j++) {
+        const int i = (int)threadIdx.x + j * BS;
+        if (i < 2 * KH + 1) KT[i] = ktv[j];
+    }
+    // offsets beyond the table's end cost +inf and never win
+    const int smin = max(-wm - 1, -kcap), smax = min(wp + 1, kcap);
+    const bool fast = smin - g >= sb && smax <= sb + 2 * KH;
+    const double* K = KT - sb;   // K[s] = k(s), s in [sb, sb + 2 KH]
+    const double gsl = a.kslack;
     __syncthreads();
 
-    const double* __restrict__ src = in + lbase;
     if (fast) {
         // sources that can reach the targets: [r0 - wp, r0 + NT - 1 + wm]
         const int pA = r0 - wp, pB = r0 + NT - 1 + wm;
@@ -570,13 +609,7 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
             for (int ch = q; ch < nch && lok; ch += BS / C) {
                 const int p0 = pA + ch * kCh;
                 double uu[kCh + 2];
-                int r = (p0 - 1) % N;
-                if (r < 0) r += N;
-#pragma unroll
-                for (int k = 0; k < kCh + 2; k++) {
-                    uu[k] = src[S * r];
-                    r = r + 1 == N ? 0 : r + 1;
-                }
+                load_chunk(p0, uu);
                 auto key = [r0](int t) { return (t - r0) * kKeyStride; };
                 if (pass == 0)
                     claim_chunk<0, kCh, GEN>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, gsl, W + c,

@@ -105,6 +105,8 @@ struct SweepArgs {
     double inv2c;               // 1 / (2c)
     double pofs;                // p / (2c) = P tau / dx
     double kslack;              // 2^-40 (1 + max |k|): rounding slack of a table's crossings
+    int kvert;                  // a caller table's minimising offset (the fast sweeps centre their cost band
+                                // on the cost's vertex: this, or P tau / dx for the mechanical cost)
     const int* win_in;          // this step's windows: [2a] = W+, [2a+1] = W- of axis a
     // batched launches: blockIdx.y is the instance; its arrays, kinetic
     // table, stats slots and windows sit at these strides from instance 0's
