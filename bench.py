@@ -233,6 +233,21 @@ def measure_hbar(torch, method, subset=None):
             "per_instance_loop_s": t_loop, "speedup_batched_vs_loop": t_loop / t_sub}
 
 
+def hbar_batched_only(torch, method, steps):
+    """The batched call alone over `steps` steps (a whole number of time
+    units, for profiling)."""
+    from paper_1210_4090_amd import workloads as wl
+    from paper_1210_4090_amd.lo import effective_H
+    bw = wl.config4()
+    T = steps * bw.tau
+    Vd = {int(s): torch.as_tensor(v, device="cuda") for s, v in bw.V_by_side.items()}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    effective_H(bw.sides, bw.P, Vd, bw.tau, T, method=method)
+    torch.cuda.synchronize()
+    return {"instances": bw.ninst, "steps": steps, "batched_s": time.perf_counter() - t0}
+
+
 def measure_hbar_autotuned(torch):
     """The batched effective-Hamiltonian call with the launch-shape tuner: a
     first call tunes every batch (and keeps the choices for the process), the
@@ -360,7 +375,8 @@ ONLY = {
     "2d": _only_2d,
     "3d": _only_3d,
     "copy": lambda torch, method, steps=None: copy_ceiling(torch),
-    "hbar": lambda torch, method, steps=None: measure_hbar(torch, method),
+    "hbar": lambda torch, method, steps=None: measure_hbar(torch, method) if not steps else hbar_batched_only(
+        torch, method, steps),
     "adjoint": lambda torch, method, steps=None: measure_adjoint(torch, method, reps=1),
     "adjoint_recorded": lambda torch, method, steps=None: measure_adjoint(torch, method, reps=1, record=True),
     "pendulum": lambda torch, method, steps=None: measure_paper_pendulum(torch, method, reps=1),
@@ -379,7 +395,8 @@ def main():
                     help="measure one workload and print its figures (for profiling runs); no "
                          "headline line")
     ap.add_argument("--run-steps", type=int, default=None,
-                    help="with --only 2d / 3d: one run of this many steps from u0")
+                    help="with --only 2d / 3d: one run of this many steps from u0; with --only hbar: the "
+                         "batched call alone over this many steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
