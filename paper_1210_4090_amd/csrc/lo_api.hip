@@ -385,6 +385,10 @@ void choose_kernels(lo_plan_t p)
             p->halo[a] = (int)std::max<int64_t>(H, 1);
             p->halo_max[a] = p->halo[a];
             p->tile_rows[a] = 0;
+            // rows of at most 1024 points in sweeps of 2^24 points or more take
+            // 4 points a thread (blocks of 512): the faster shape on every such
+            // grid timed (256^3; batches of 512^2, 768^2 and 1024^2 grids)
+            p->row_ch[a] = N <= 1024 && p->npts * p->nb >= ((int64_t)1 << 24) ? 4 : 8;
         } else {
             p->kind[a] = kKindTile;
             int R = p->fast[a] ? tile_len(p, a, true) : (int)std::min<int64_t>(N, 128);
@@ -795,8 +799,8 @@ lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
     const int64_t t0 = n0 + kTuneWarm;
     TuneChoice def, alt, best;
     for (int a = 0; a < kMaxDim; a++) {
-        def.row_ch[a] = 8;
-        alt.row_ch[a] = 4;
+        def.row_ch[a] = a < p->ndim ? p->row_ch[a] : 8;
+        alt.row_ch[a] = 12 - def.row_ch[a];
         const bool wide = a < p->ndim && (p->halo[a] >= 40 || a == p->ndim - 1);
         def.tile_fix[a] = a < p->ndim && p->kind[a] == kKindTile ? tile_len(p, a, wide) : 0;
         alt.tile_fix[a] = a < p->ndim && p->kind[a] == kKindTile ? tile_len(p, a, !wide) : 0;
