@@ -29,10 +29,53 @@ __device__ __forceinline__ double dec(uint64_t k)
 
 __device__ __forceinline__ uint64_t enc_neg_inf() { return ~(uint64_t)0xFFF0000000000000ull; }
 
+// One DPP move of a double (both halves with the same control); lanes without
+// a source keep their own value.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)b, hi = (int)(b >> 32);
+    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false);
+    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)h2 << 32) | (unsigned)l2));
+}
+
+// Wave maximum through row shifts and row broadcasts; valid in lane 63 only.
+__device__ __forceinline__ double wave_max_to63(double v)
+{
+    v = fmax(v, dpp_move<0x111, 0xf>(v));   // row_shr:1
+    v = fmax(v, dpp_move<0x112, 0xf>(v));   // row_shr:2
+    v = fmax(v, dpp_move<0x114, 0xf>(v));   // row_shr:4
+    v = fmax(v, dpp_move<0x118, 0xf>(v));   // row_shr:8  -> lane 15 of each row: row max
+    v = fmax(v, dpp_move<0x142, 0xa>(v));   // row_bcast:15 into rows 1, 3
+    v = fmax(v, dpp_move<0x143, 0xc>(v));   // row_bcast:31 into rows 2, 3 -> lane 63: wave max
+    return v;
+}
+
+// Wave maximum in every lane: the row shifts and broadcasts above, then lane
+// 63 read out (register moves only; a butterfly of lane shuffles would take
+// six LDS round trips).
 __device__ __forceinline__ double wave_max(double v)
 {
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-    return v;
+    const long long b = __double_as_longlong(wave_max_to63(v));
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, kWave - 1);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), kWave - 1);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Largest v >= 0 over the block into *dst with one global atomic (many
+// blocks contending on one address cost far more than a block's barrier).
+// Every thread of the block calls it.
+__device__ inline void block_atomic_max(int v, uint32_t* dst)
+{
+    __shared__ int s;
+    if (threadIdx.x == 0) s = 0;
+    __syncthreads();
+    v = (int)wave_max((double)v);
+    if (threadIdx.x % kWave == 0 && v > 0) atomicMax(&s, v);
+    __syncthreads();
+    if (threadIdx.x == 0 && s > 0) atomicMax(dst, (uint32_t)s);
 }
 
 // Block-wide max of three values (blockDim <= 512); result in every thread.
@@ -95,44 +138,6 @@ __device__ inline void block_max5(double& a, double& b, double& c, double& d, do
     __syncthreads();
 }
 
-// One DPP move of a double (both halves with the same control); lanes without
-// a source keep their own value.
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_move(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = (int)b, hi = (int)(b >> 32);
-    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false);
-    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false);
-    return __longlong_as_double((long long)(((unsigned long long)(unsigned)h2 << 32) | (unsigned)l2));
-}
-
-// Wave maximum through row shifts and row broadcasts; valid in lane 63 only.
-__device__ __forceinline__ double wave_max_to63(double v)
-{
-    v = fmax(v, dpp_move<0x111, 0xf>(v));   // row_shr:1
-    v = fmax(v, dpp_move<0x112, 0xf>(v));   // row_shr:2
-    v = fmax(v, dpp_move<0x114, 0xf>(v));   // row_shr:4
-    v = fmax(v, dpp_move<0x118, 0xf>(v));   // row_shr:8  -> lane 15 of each row: row max
-    v = fmax(v, dpp_move<0x142, 0xa>(v));   // row_bcast:15 into rows 1, 3
-    v = fmax(v, dpp_move<0x143, 0xc>(v));   // row_bcast:31 into rows 2, 3 -> lane 63: wave max
-    return v;
-}
-
-// Largest v >= 0 over the block into *dst with one global atomic (many
-// blocks contending on one address cost far more than a block's barrier).
-// Every thread of the block calls it.
-__device__ inline void block_atomic_max(int v, uint32_t* dst)
-{
-    __shared__ int s;
-    if (threadIdx.x == 0) s = 0;
-    __syncthreads();
-    v = (int)wave_max((double)v);
-    if (threadIdx.x % kWave == 0 && v > 0) atomicMax(&s, v);
-    __syncthreads();
-    if (threadIdx.x == 0 && s > 0) atomicMax(dst, (uint32_t)s);
-}
-
 // Block-wide max of five values, valid in thread 0 only (red: 40 doubles).
 __device__ inline void block_max5_to0(double& a, double& b, double& c, double& d, double& e, double* red)
 {
@@ -178,12 +183,6 @@ __device__ __forceinline__ void clear_slot(uint64_t* slot)
 __device__ __forceinline__ void stat_put(uint64_t* slot, int w, double v)
 {
     atomicMax((unsigned long long*)&slot[w * kSpread + (int)(blockIdx.x % kSpread)], (unsigned long long)enc(v));
-}
-
-// Max over the sub-slots of word `w`; every lane of a full wave must call it.
-__device__ __forceinline__ double stat_get(const uint64_t* slot, int w)
-{
-    return wave_max(dec(slot[w * kSpread + threadIdx.x % kWave]));
 }
 
 // A wave-uniform 64-bit value moved to scalar registers, so that pointers
@@ -237,7 +236,7 @@ __device__ __forceinline__ int64_t remap_block(int64_t b, int64_t G)
 // mechanical cost evaluated in place (the same operations as the table's,
 // so the same values, without a memory round trip per probe).
 template <class KF>
-__device__ inline int window_side(KF kf, int64_t kcap, int dir, double D, double sbase, bool level, int64_t est,
+__device__ __forceinline__ int window_side(KF kf, int64_t kcap, int dir, double D, double sbase, bool level, int64_t est,
                                   bool* cap)
 {
     const int lane = threadIdx.x % kWave;
@@ -298,58 +297,82 @@ __device__ __forceinline__ double mech_cost_dev(int64_t s, double dx, double tau
 
 // Windows of every axis for the next step of instance `inst` (its kinetic
 // tables at inst * bk[a]), from the statistics in `slot` (recorded by the
-// step's sweep kernels, which have all completed).  Wave w of the block runs
-// one of the four one-sided searches of each axis: the neighbour bound and the
-// oscillation bound on each side; the window is the smaller of the two.
-__device__ inline void next_windows(const WinParams& P, int64_t inst, const uint64_t* slot, int* win_out,
+// step's sweep kernels, which have all completed).  All of its global loads
+// go out at once: wave w reduces statistics words w, w + nwaves, ... (one
+// sub-slot a lane) and wave 0 copies the parameters into LDS.  Then the four
+// one-sided searches of each axis (the neighbour bound and the oscillation
+// bound on each side) are dealt to the waves; the window is the smaller of
+// the two bounds on each side.  Every thread of the block calls it.
+__device__ inline void next_windows(const WinParams& Pg, int64_t inst, const uint64_t* slot, int* win_out,
                                     uint32_t* flags)
 {
+    constexpr int kWords = 9;   // [a] max fwd diff, [3 + a] max -fwd diff, [6] max|w|, [7] max u, [8] max -u
+    constexpr int kParamWords = (int)(sizeof(WinParams) / 8);
+    static_assert(sizeof(WinParams) % 8 == 0 && kParamWords <= kWave, "one wave copies the parameters");
+    __shared__ double sw[kWords];
+    __shared__ uint64_t spw[kParamWords];
     __shared__ int part[kMaxDim][4];
     __shared__ int caps[kMaxDim][4];
-    const int w = threadIdx.x / kWave;
-    const double M = stat_get(slot, 6) + (P.lag ? P.slack_extra : 0.0);
-    const double osc0 = stat_get(slot, 7) + stat_get(slot, 8) + (P.lag ? P.hv_osc : 0.0);
-    if (w < 4) {
-        const int dir = (w < 2) ? 1 : -1;
-        const bool level = (w & 1) != 0;
-        // every axis' statistic first, so that their loads overlap
-        double dst[kMaxDim] = {0.0, 0.0, 0.0};
-        if (!level)
-            for (int ax = 0; ax < P.ndim; ax++) dst[ax] = stat_get(slot, dir > 0 ? ax : 3 + ax);
-        for (int ax = 0; ax < P.ndim; ax++) {
-            if (P.wfix[ax] > 0) continue;
-            double D;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, nwv = blockDim.x / kWave;
+    {
+        uint64_t v[3];   // every caller's blocks have 4 waves or more: at most 3 words a wave
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const int k = w + i * nwv;
+            v[i] = k < kWords ? slot[k * kSpread + lane] : 0;
+        }
+        uint64_t pw = 0;
+        if (w == 0 && lane < kParamWords) pw = ((const uint64_t*)&Pg)[lane];
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const int k = w + i * nwv;
+            if (k < kWords) {
+                const double m = wave_max_to63(dec(v[i]));
+                if (lane == kWave - 1) sw[k] = m;
+            }
+        }
+        if (w == 0 && lane < kParamWords) spw[lane] = pw;
+    }
+    __syncthreads();
+    const WinParams& P = *(const WinParams*)spw;
+    const double M = sw[6] + (P.lag ? P.slack_extra : 0.0);
+    const double osc0 = sw[7] + sw[8] + (P.lag ? P.hv_osc : 0.0);
+    for (int t = w; t < 4 * P.ndim; t += nwv) {
+        const int ax = t >> 2, kind = t & 3;
+        const int dir = kind < 2 ? 1 : -1;
+        const bool level = (kind & 1) != 0;
+        if (P.wfix[ax] > 0) continue;
+        double D;
+        if (level)
+            D = osc0 + P.osc_extra[ax];
+        else
+            D = sw[dir > 0 ? ax : 3 + ax] + (dir > 0 ? P.dvf[ax] : P.dvb[ax]) * (P.lag ? 2.0 : 1.0);
+        const double sbase = 1.0 + M + P.slack_extra;
+        int64_t est = 0;
+        if (P.quad[ax]) {
+            const double po = P.pofs_b ? P.pofs_b[inst * kMaxDim + ax] : P.pofs[ax];
+            const double c = P.cq[ax], p = 2.0 * P.cq[ax] * po * (double)dir;
+            double e;
             if (level)
-                D = osc0 + P.osc_extra[ax];
+                e = (p + sqrt(fmax(p * p + 4.0 * c * fmax(D, 0.0), 0.0))) / (2.0 * c);
             else
-                D = dst[ax] + (dir > 0 ? P.dvf[ax] : P.dvb[ax]) * (P.lag ? 2.0 : 1.0);
-            const double sbase = 1.0 + M + P.slack_extra;
-            int64_t est = 0;
-            if (P.quad[ax]) {
-                const double po = P.pofs_b ? P.pofs_b[inst * kMaxDim + ax] : P.pofs[ax];
-                const double c = P.cq[ax], p = 2.0 * P.cq[ax] * po * (double)dir;
-                double e;
-                if (level)
-                    e = (p + sqrt(fmax(p * p + 4.0 * c * fmax(D, 0.0), 0.0))) / (2.0 * c);
-                else
-                    e = (D + p) / (2.0 * c) + 0.5;
-                if (e > 0.0 && e < 1e9) est = (int64_t)e;
-            }
-            bool cap = false;
-            int r;
-            if (P.quad[ax]) {
-                const double dx = P.dx[ax], tau = P.tau;
-                const double Pa = P.P_b ? P.P_b[inst * kMaxDim + ax] : P.P[ax];
-                r = window_side([=](int64_t s) { return mech_cost_dev(s, dx, tau, Pa); }, P.kcap[ax], dir, D, sbase,
-                                level, est, &cap);
-            } else {
-                const double* __restrict__ kt = P.k[ax] + inst * P.bk[ax];
-                r = window_side([=](int64_t s) { return kt[s]; }, P.kcap[ax], dir, D, sbase, level, est, &cap);
-            }
-            if (threadIdx.x % kWave == 0) {
-                part[ax][w] = r;
-                caps[ax][w] = cap ? 1 : 0;
-            }
+                e = (D + p) / (2.0 * c) + 0.5;
+            if (e > 0.0 && e < 1e9) est = (int64_t)e;
+        }
+        bool cap = false;
+        int r;
+        if (P.quad[ax]) {
+            const double dx = P.dx[ax], tau = P.tau;
+            const double Pa = P.P_b ? P.P_b[inst * kMaxDim + ax] : P.P[ax];
+            r = window_side([=](int64_t s) { return mech_cost_dev(s, dx, tau, Pa); }, P.kcap[ax], dir, D, sbase,
+                            level, est, &cap);
+        } else {
+            const double* __restrict__ kt = P.k[ax] + inst * P.bk[ax];
+            r = window_side([=](int64_t s) { return kt[s]; }, P.kcap[ax], dir, D, sbase, level, est, &cap);
+        }
+        if (lane == 0) {
+            part[ax][kind] = r;
+            caps[ax][kind] = cap ? 1 : 0;
         }
     }
     __syncthreads();
