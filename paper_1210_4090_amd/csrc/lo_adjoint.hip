@@ -17,6 +17,7 @@
 // line whose staged offsets are not monotone (possible only through rounding
 // near exact ties) is summed by scanning every target within the halo.
 #include <algorithm>
+#include <type_traits>
 
 #include "lo_device.h"
 
@@ -109,6 +110,21 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int16_t* __restrict__ 
             }
         }
     }
+    // Lam (the running sum of gradients that the potential's coefficients
+    // need) of this thread's sources, loaded now so that the latency passes
+    // during the marking: when a thread serves one line and at most kLamPf
+    // sources of it
+    constexpr int kLamPf = 8;
+    const bool lam_pf = Lam != nullptr && c_hi - c_lo == 1 && R <= kLamPf * Q;
+    double lamv[kLamPf];
+    if (lam_pf && lb * C + c_lo < a.g.nlines) {
+        const int64_t base = line_base(lb * C + c_lo, S, N);
+#pragma unroll
+        for (int i = 0; i < kLamPf; i++) {
+            const int j = q0 + i * Q;
+            lamv[i] = j < Rt ? Lam[base + (int64_t)(r0 + j) * S] : 0.0;
+        }
+    }
     if (bad) atomicOr(&flags[0], kErrAdjointHalo);
     __syncthreads();
 
@@ -129,37 +145,70 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int16_t* __restrict__ 
     }
     __syncthreads();
 
-    for (int c = c_lo; c < c_hi; c++) {
-        const int ln = lb * C + c;
-        if (ln >= a.g.nlines) continue;
-        const int64_t base = line_base(ln, S, N);
+    // the sum of the run of targets of source j of line c of the tile
+    auto run_sum = [&](int c, int j) -> double {
         const int16_t* el = es + c * span;
         const double* ll = ls + c * span;
-        const bool mono = nonmono[c] == 0;
-        for (int j = q0; j < Rt; j += Q) {
-            double acc = 0.0;
-            if (mono) {
-                const int f = first[c * R + j];
-                if (f >= 0) {
-                    const int l = last[c * R + j];
-                    // targets in increasing residue order: when the run crosses a
-                    // multiple of N, the part at or above it comes first
-                    const int Tf = T0 + f;
-                    const int kN = (floor_div(Tf, N) + 1) * N;
-                    const int split = (kN <= T0 + l) ? kN - T0 : f;   // first position of the upper part
-                    for (int p = split; p <= l; p++) acc = acc + ll[p];
-                    for (int p = f; p < split; p++) acc = acc + ll[p];
-                }
-            } else {
-                const int pe = min(j + 2 * h, span - 1);
-                for (int p = j; p <= pe; p++)
-                    if (p - h + el[p] == j) acc = acc + ll[p];
+        double acc = 0.0;
+        if (nonmono[c] == 0) {
+            const int f = first[c * R + j];
+            if (f >= 0) {
+                const int l = last[c * R + j];
+                // targets in increasing residue order: when the run crosses a
+                // multiple of N, the part at or above it comes first
+                const int Tf = T0 + f;
+                const int kN = (floor_div(Tf, N) + 1) * N;
+                const int split = (kN <= T0 + l) ? kN - T0 : f;   // first position of the upper part
+                for (int p = split; p <= l; p++) acc = acc + ll[p];
+                for (int p = f; p < split; p++) acc = acc + ll[p];
             }
-            const int64_t x = base + (int64_t)(r0 + j) * S;
-            out[x] = acc;
-            if (Lam) Lam[x] = Lam[x] + ll[h + j];
+        } else {
+            const int pe = min(j + 2 * h, span - 1);
+            for (int p = j; p <= pe; p++)
+                if (p - h + el[p] == j) acc = acc + ll[p];
         }
-    }
+        return acc;
+    };
+    auto emit = [&](auto wt_tag) {
+        constexpr bool kWt = decltype(wt_tag)::value;
+        auto put = [](double* q, double v) {
+            if constexpr (kWt)
+                __hip_atomic_store(q, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                *q = v;
+        };
+        if (lam_pf) {
+            const int c = c_lo, ln = lb * C + c;
+            if (ln >= a.g.nlines) return;
+            const int64_t base = line_base(ln, S, N);
+            const double* ll = ls + c * span;
+#pragma unroll
+            for (int i = 0; i < kLamPf; i++) {
+                const int j = q0 + i * Q;
+                if (j < Rt) {
+                    const int64_t x = base + (int64_t)(r0 + j) * S;
+                    put(out + x, run_sum(c, j));
+                    put(Lam + x, lamv[i] + ll[h + j]);
+                }
+            }
+            return;
+        }
+        for (int c = c_lo; c < c_hi; c++) {
+            const int ln = lb * C + c;
+            if (ln >= a.g.nlines) continue;
+            const int64_t base = line_base(ln, S, N);
+            const double* ll = ls + c * span;
+            for (int j = q0; j < Rt; j += Q) {
+                const int64_t x = base + (int64_t)(r0 + j) * S;
+                put(out + x, run_sum(c, j));
+                if (Lam) put(Lam + x, Lam[x] + ll[h + j]);
+            }
+        }
+    };
+    if (a.wt)
+        emit(std::true_type{});
+    else
+        emit(std::false_type{});
 }
 
 // Deterministic block sum (fixed shuffle pattern, waves combined in order).
@@ -238,6 +287,10 @@ bool scatter_layout(const AxisGeom& g, int h, size_t lds_max, ScatterArgs* a)
     a->C = C;
     a->R = R;
     a->span = R + 2 * h;
+    // a grid that fits the last-level caches is written through them when a
+    // store instruction covers whole lines (unit stride, or 16 lines side by
+    // side): the kernel's end then has little to write back
+    a->wt = g.n * g.nlines <= ((int64_t)1 << 22) && (g.stride == 1 || C >= 16) ? 1 : 0;
     return true;
 }
 
@@ -266,17 +319,16 @@ hipError_t launch_project(const double* Lam, const double* basis, int M, int64_t
 
 namespace {
 
-// Largest |offset| of each axis in a record of int16 argmins laid out
-// [step][axis][npts].  Block x takes part x % G of segment (step, axis)
-// x / G; one global atomic a block.
+// Largest |offset| of every (step, axis) segment of a record of int16
+// argmins laid out [step][axis][npts], into out[step * ndim + axis].  Block x
+// takes part x % G of segment x / G; one global atomic a block.
 // V8: npts a multiple of 8, 16-byte loads of 8 offsets.
 template <bool V8>
-__global__ __launch_bounds__(kBlock) void k_absmax16(const int16_t* __restrict__ E, int64_t npts, int ndim, int G,
+__global__ __launch_bounds__(kBlock) void k_absmax16(const int16_t* __restrict__ E, int64_t npts, int G,
                                                      uint32_t* __restrict__ out)
 {
     const int64_t seg = blockIdx.x / G;
     const int part = (int)(blockIdx.x - seg * G);
-    const int a = (int)(seg % ndim);
     const int16_t* base = E + seg * npts;
     uint32_t mx = 0;
     if (V8) {
@@ -294,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_absmax16(const int16_t* __restrict__
         for (int64_t i = (int64_t)part * kBlock + threadIdx.x; i < npts; i += (int64_t)G * kBlock)
             mx = max(mx, (uint32_t)abs((int)base[i]));
     }
-    block_atomic_max((int)mx, &out[a]);
+    block_atomic_max((int)mx, &out[seg]);
 }
 
 }  // namespace
@@ -308,9 +360,9 @@ hipError_t launch_absmax16(const int16_t* E, int64_t steps, int ndim, int64_t np
     const int G = (int)std::max<int64_t>(1, std::min<int64_t>(per, (2048 + nseg - 1) / nseg));
     if (nseg * G > 0x7fffffff) return hipErrorInvalidValue;
     if (npts % 8 == 0)
-        hipLaunchKernelGGL(k_absmax16<true>, dim3((unsigned)(nseg * G)), dim3(kBlock), 0, s, E, npts, ndim, G, out);
+        hipLaunchKernelGGL(k_absmax16<true>, dim3((unsigned)(nseg * G)), dim3(kBlock), 0, s, E, npts, G, out);
     else
-        hipLaunchKernelGGL(k_absmax16<false>, dim3((unsigned)(nseg * G)), dim3(kBlock), 0, s, E, npts, ndim, G, out);
+        hipLaunchKernelGGL(k_absmax16<false>, dim3((unsigned)(nseg * G)), dim3(kBlock), 0, s, E, npts, G, out);
     return hipGetLastError();
 }
 

@@ -93,6 +93,8 @@ struct lo_plan_s {
     int16_t* bw_arg = nullptr;       // argmins of two segments [2][steps][ndim][npts]
     int64_t bw_arg_steps = 0;        // steps of one of them
     uint32_t* bw_err = nullptr;      // error bits of the reverse sweeps
+    uint32_t* bw_amax = nullptr;     // largest |offset| of every (step, axis) whose scatter follows
+    int64_t bw_amax_words = 0;
     hipStream_t bw_stream = nullptr; // lo_backward: segment recomputes, beside the reverse sweeps
     hipEvent_t bw_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // start, recomputed[2], reversed[2]
     double* bw_part = nullptr;       // projection partial sums [nmodes][blocks] + [nmodes]
@@ -176,6 +178,7 @@ void free_plan(lo_plan_t p)
     if (p->bw_Lam) (void)hipFree(p->bw_Lam);
     if (p->bw_arg) (void)hipFree(p->bw_arg);
     if (p->bw_err) (void)hipFree(p->bw_err);
+    if (p->bw_amax) (void)hipFree(p->bw_amax);
     for (auto& e : p->bw_ev)
         if (e) (void)hipEventDestroy(e);
     if (p->bw_stream) (void)hipStreamDestroy(p->bw_stream);
@@ -512,7 +515,7 @@ lo_status adapt_from_flags(lo_plan_t p, hipStream_t s)
 }
 
 lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipStream_t s,
-                       hipEvent_t* ev = nullptr)
+                       hipEvent_t* ev = nullptr, uint32_t* amax_out = nullptr)
 {
     const double* hv = p->has_v ? p->dhv : nullptr;
     if (p->time_dep) {
@@ -556,6 +559,7 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         A.flags = p->flags;
         A.hv = a == p->ndim - 1 ? hv : nullptr;
         A.argmin = argmin ? argmin + (size_t)a * p->npts : nullptr;
+        A.amax_out = argmin ? amax_out : nullptr;
         A.halo = p->halo[a];
         A.tile_rows = p->tile_rows[a];
         if (argmin && p->fast[a]) {
@@ -564,6 +568,11 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
             if (p->kind[a] == kKindTile) A.tile_rows = p->halo[a] >= 40 ? 256 : 128;
         }
         A.fast = p->fast[a] ? 1 : 0;
+        // a grid whose u fits the last-level caches of the XCDs (2^22 points, 32 MB)
+        // is written through them by the tile sweeps: the kernel's end then has
+        // little to write back (a larger grid's dirty lines leave the caches
+        // during the sweep anyway, and writing through costs it time)
+        A.wt = p->npts * p->nb <= ((int64_t)1 << 22) ? 1 : 0;
         A.quad = p->user_table[a] ? 0 : 1;
         A.cq = p->dx[a] * p->dx[a] / (2.0 * p->d.tau);
         A.inv2c = 1.0 / (2.0 * A.cq);
@@ -648,6 +657,18 @@ lo_status backward_buffers(lo_plan_t p, int64_t steps, bool coef)
         st = alloc((void**)&p->bw_arg, sizeof(int16_t) * 2 * (size_t)steps * p->ndim * p->npts);
         if (!st) p->bw_arg_steps = steps;
     }
+    return st;
+}
+
+// At least `words` words for the per-(step, axis) largest offsets.
+lo_status amax_buffer(lo_plan_t p, int64_t words)
+{
+    if (words <= p->bw_amax_words) return LO_OK;
+    if (p->bw_amax) (void)hipFree(p->bw_amax);
+    p->bw_amax = nullptr;
+    p->bw_amax_words = 0;
+    lo_status st = alloc((void**)&p->bw_amax, sizeof(uint32_t) * (size_t)std::max<int64_t>(words, 1));
+    if (!st) p->bw_amax_words = words;
     return st;
 }
 
@@ -1334,27 +1355,31 @@ lo_status lo_effective_H(int32_t ninst, const lo_desc* descs, const lo_potential
 
 namespace {
 
-// Scatter layouts of every axis for offsets up to amax[a].
-lo_status scatter_layouts(lo_plan_t p, const uint32_t* amax, ScatterArgs* sa)
+// Scatter layouts of `steps` steps, every axis of step k for offsets up to
+// amax[k * ndim + a] (each step's own largest offsets: the first steps of a
+// run from smooth data reach several times further than the later ones).
+lo_status scatter_layouts(lo_plan_t p, const uint32_t* amax, int64_t steps, ScatterArgs* sa)
 {
     int dev = 0, lds_max = 65536;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return LO_ERR_HIP;
-    for (int a = 0; a < p->ndim; a++) {
+    for (int64_t i = 0; i < steps * p->ndim; i++) {
+        const int a = (int)(i % p->ndim);
         AxisGeom g;
         g.n = p->n[a];
         g.stride = 1;
         for (int b = 0; b < a; b++) g.stride *= p->n[b];
         g.nlines = p->npts / p->n[a];
-        if (!scatter_layout(g, (int)amax[a], (size_t)lds_max, &sa[a])) return LO_ERR_UNSUPPORTED;
+        if (!scatter_layout(g, (int)amax[i], (size_t)lds_max, &sa[i])) return LO_ERR_UNSUPPORTED;
     }
     return LO_OK;
 }
 
-// Reverse of steps n1-1 .. n0 whose argmins are E[(n - n0)][a][npts]: axes
-// d-1 .. 0, the adjoint of u^{n+1} entering the potential's gradient before
-// the sweeps are undone.  lam ping-pongs between the plan's two buffers.
+// Reverse of steps n1-1 .. n0 whose argmins are E[(n - n0)][a][npts] and
+// scatter layouts sa[(n - n0) * ndim + a]: axes d-1 .. 0, the adjoint of
+// u^{n+1} entering the potential's gradient before the sweeps are undone.
+// lam ping-pongs between the plan's two buffers.
 lo_status reverse_steps(lo_plan_t p, const int16_t* E, int64_t n0, int64_t n1, const ScatterArgs* sa, int* cur,
                         bool coef, hipStream_t s)
 {
@@ -1362,7 +1387,8 @@ lo_status reverse_steps(lo_plan_t p, const int16_t* E, int64_t n0, int64_t n1, c
         for (int a = p->ndim - 1; a >= 0; a--) {
             const int16_t* Ea = E + ((size_t)(n - n0) * p->ndim + a) * p->npts;
             double* Lam = (coef && a == p->ndim - 1) ? p->bw_Lam : nullptr;
-            HIPCHK(launch_scatter(Ea, p->bw_lam[*cur], p->bw_lam[*cur ^ 1], Lam, sa[a], p->bw_err, s));
+            HIPCHK(launch_scatter(Ea, p->bw_lam[*cur], p->bw_lam[*cur ^ 1], Lam, sa[(n - n0) * p->ndim + a],
+                                  p->bw_err, s));
             *cur ^= 1;
         }
     }
@@ -1421,6 +1447,7 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
     StreamDrain drain{s};
     const int64_t seg = std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1));
     st = backward_buffers(p, seg, grad_coef != nullptr);
+    if (!st) st = amax_buffer(p, 2 * seg * p->ndim);
     if (st) return st;
     if (!p->bw_stream) HIPCHK(hipStreamCreateWithFlags(&p->bw_stream, hipStreamNonBlocking));
     for (auto& e : p->bw_ev)
@@ -1438,30 +1465,37 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
     HIPCHK(hipStreamWaitEvent(s2, p->bw_ev[0], 0));
     uint32_t hf[8] = {0};
     uint32_t errs = 0;
-    ScatterArgs sa[2][kMaxDim];
+    std::vector<ScatterArgs> sa[2];
+    std::vector<uint32_t> am((size_t)seg * p->ndim);
     // Segment k recomputed from its checkpoint (on s2) with every sweep's
-    // argmins in buffer k % 2; its largest offsets size its scatter tiles.
+    // argmins in buffer k % 2; each step's largest offsets size its scatter
+    // tiles.
     auto recompute = [&](int64_t k) -> lo_status {
         const int64_t n0 = k * ckpt_every, n1 = std::min(nsteps, n0 + ckpt_every);
         int16_t* E = p->bw_arg + (size_t)(k % 2) * seg_arg;
+        uint32_t* AM = p->bw_amax + (size_t)(k % 2) * seg * p->ndim;
+        const size_t am_words = (size_t)(n1 - n0) * p->ndim;
         HIPCHK(hipMemcpyAsync(p->bw_u, ckpt + (size_t)k * p->npts, bytes, hipMemcpyDeviceToDevice, s2));
+        HIPCHK(launch_fill_u32(AM, (int64_t)am_words, 0u, s2));
         lo_status r = prologue(p, p->bw_u, n0, s2);
         for (int64_t n = n0; n < n1 && !r; n++) {
             if (n > n0 && (n - n0) % kGraphSteps == 0) r = adapt_from_flags(p, s2);
-            if (!r) r = enqueue_step(p, p->bw_u, n, E + (size_t)(n - n0) * p->ndim * p->npts, s2);
+            if (!r)
+                r = enqueue_step(p, p->bw_u, n, E + (size_t)(n - n0) * p->ndim * p->npts, s2, nullptr,
+                                 AM + (n - n0) * p->ndim);
         }
         if (r) return r;
         uint32_t f[kFlagWords];
         HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(f), hipMemcpyDeviceToHost, s2));
+        HIPCHK(hipMemcpyAsync(am.data(), AM, sizeof(uint32_t) * am_words, hipMemcpyDeviceToHost, s2));
         HIPCHK(hipStreamSynchronize(s2));
         errs |= f[0];
         if (f[0] & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrArgRange)) return LO_ERR_WINDOW;
-        for (int a = 0; a < p->ndim; a++) {
-            hf[1 + a] = std::max(hf[1 + a], std::max(p->hflags[1 + a], fold_window(f, a)));
-            hf[4 + a] = std::max(hf[4 + a], f[4 + a]);
-        }
+        for (int a = 0; a < p->ndim; a++) hf[1 + a] = std::max(hf[1 + a], std::max(p->hflags[1 + a], fold_window(f, a)));
+        for (size_t i = 0; i < am_words; i++) hf[4 + i % p->ndim] = std::max(hf[4 + i % p->ndim], am[i]);
         HIPCHK(hipEventRecord(p->bw_ev[1 + k % 2], s2));
-        return scatter_layouts(p, f + 4, sa[k % 2]);
+        sa[k % 2].resize(am_words);
+        return scatter_layouts(p, am.data(), n1 - n0, sa[k % 2].data());
     };
     // Segments are undone from the last.  The reverse sweeps of segment k (on
     // s) run while segment k - 1 is recomputed (on s2) into the other buffer,
@@ -1471,8 +1505,8 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
     for (int64_t k = nseg - 1; k >= 0 && !st; k--) {
         const int64_t n0 = k * ckpt_every, n1 = std::min(nsteps, n0 + ckpt_every);
         HIPCHK(hipStreamWaitEvent(s, p->bw_ev[1 + k % 2], 0));
-        st = reverse_steps(p, p->bw_arg + (size_t)(k % 2) * seg_arg, n0, n1, sa[k % 2], &cur, grad_coef != nullptr,
-                           s);
+        st = reverse_steps(p, p->bw_arg + (size_t)(k % 2) * seg_arg, n0, n1, sa[k % 2].data(), &cur,
+                           grad_coef != nullptr, s);
         if (st) break;
         HIPCHK(hipEventRecord(p->bw_ev[3 + k % 2], s));
         if (k > 0) {
@@ -1508,6 +1542,7 @@ lo_status lo_backward_recorded(lo_plan_t p, const int16_t* argmins, int64_t nste
     hipStream_t s = (hipStream_t)stream;
     StreamDrain drain{s};
     st = backward_buffers(p, 1, grad_coef != nullptr);
+    if (!st) st = amax_buffer(p, nsteps * p->ndim);
     if (st) return st;
     const size_t bytes = sizeof(double) * (size_t)p->npts;
     int cur = 0;
@@ -1515,16 +1550,20 @@ lo_status lo_backward_recorded(lo_plan_t p, const int16_t* argmins, int64_t nste
     if (grad_coef) HIPCHK(hipMemsetAsync(p->bw_Lam, 0, bytes, s));
     HIPCHK(hipMemsetAsync(p->flags, 0, sizeof(uint32_t) * kFlagWords, s));
     HIPCHK(hipMemsetAsync(p->bw_err, 0, sizeof(uint32_t), s));
-    // the largest offset of each axis sizes the scatter tiles' halos
-    HIPCHK(launch_absmax16(argmins, nsteps, p->ndim, p->npts, p->flags + 4, s));
-    uint32_t f[kFlagWords];
-    HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(f), hipMemcpyDeviceToHost, s));
+    // each step's largest offsets size its scatter tiles' halos
+    const size_t am_words = (size_t)nsteps * p->ndim;
+    std::vector<uint32_t> am(am_words);
+    if (nsteps > 0) {
+        HIPCHK(launch_fill_u32(p->bw_amax, (int64_t)am_words, 0u, s));
+        HIPCHK(launch_absmax16(argmins, nsteps, p->ndim, p->npts, p->bw_amax, s));
+        HIPCHK(hipMemcpyAsync(am.data(), p->bw_amax, sizeof(uint32_t) * am_words, hipMemcpyDeviceToHost, s));
+    }
     HIPCHK(hipStreamSynchronize(s));
     uint32_t hf[8] = {0};
-    for (int a = 0; a < p->ndim; a++) hf[4 + a] = f[4 + a];
-    ScatterArgs sa[kMaxDim];
-    st = scatter_layouts(p, f + 4, sa);
-    if (!st) st = reverse_steps(p, argmins, 0, nsteps, sa, &cur, grad_coef != nullptr, s);
+    for (size_t i = 0; i < am_words; i++) hf[4 + i % p->ndim] = std::max(hf[4 + i % p->ndim], am[i]);
+    std::vector<ScatterArgs> sa(am_words);
+    st = scatter_layouts(p, am.data(), nsteps, sa.data());
+    if (!st) st = reverse_steps(p, argmins, 0, nsteps, sa.data(), &cur, grad_coef != nullptr, s);
     return finish_backward(p, cur, grad_u0, grad_coef, 0, hf, st, s);
 }
 

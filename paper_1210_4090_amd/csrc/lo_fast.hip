@@ -58,6 +58,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 
 namespace lo {
@@ -75,6 +76,19 @@ constexpr double kEps = 1e-6;    // claim widening, in cells
 // chunk, so lanes that walk chunk-strided keys hit distinct banks
 template <int CH>
 __device__ __forceinline__ int skc(int x) { return x + (int)((unsigned)x / CH); }
+
+// An output store, written through the L2 at agent scope when WT (a grid
+// that fits the caches: the kernel's end then has little to write back).
+// The tile kernels' stores cover whole cache lines (16 adjacent lines, or
+// consecutive targets), which is what makes writing through cheap.
+template <bool WT>
+__device__ __forceinline__ void put(double* p, double v)
+{
+    if constexpr (WT)
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
 
 }  // namespace
 
@@ -487,7 +501,7 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
     }
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
     if (ARG && a.argmin) {
-        block_atomic_max(amax, &a.flags[4 + a.axis]);
+        block_atomic_max(amax, a.amax_out ? a.amax_out + a.axis : &a.flags[4 + a.axis]);
         if (amax > 32767) atomicOr(&a.flags[0], kErrArgRange);   // stored offsets wrapped: unusable
     }
     publish_stats<EPI>(st, a, red);
@@ -661,7 +675,10 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
     SweepStats st;
     int amax = 0;
     bool bad = false;
-    if (lok) {
+    // the store kind is a compile-time choice inside the loops (one copy each)
+    auto emit = [&](auto wt_tag) {
+        constexpr bool kWt = decltype(wt_tag)::value;
+        if (!lok) return;
         double* __restrict__ dst = out + lbase + (int64_t)S * r0;
         const double* __restrict__ hv = EPI ? a.hv + lbase + (int64_t)S * r0 : nullptr;
         int16_t* am = (ARG && a.argmin) ? a.argmin + lbase + (int64_t)S * r0 : nullptr;
@@ -674,7 +691,7 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
                     const double x = W[t * kKeyStride + c];
                     bad |= !(x < INFINITY);
                     const double z = x - hvp[i];
-                    dst[off] = z;
+                    put<kWt>(dst + off, z);
                     if (a.stats_out) fold_stats<EPI>(st, x, W[(t + 1) * kKeyStride + c], z);
                 }
                 off += S * (BS / C);
@@ -684,7 +701,7 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
                 const double x = W[t * kKeyStride + c];
                 bad |= !(x < INFINITY);
                 const double z = EPI ? x - hv[off] : x;
-                dst[off] = z;
+                put<kWt>(dst + off, z);
                 if (ARG && am) {
                     const int e = A[t * kKeyStride + c];
                     am[off] = (int16_t)e;
@@ -694,10 +711,14 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
                 off += S * (BS / C);
             }
         }
-    }
+    };
+    if (C == kTileLines && a.wt)
+        emit(std::true_type{});
+    else
+        emit(std::false_type{});
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
     if (ARG && a.argmin) {
-        block_atomic_max(amax, &a.flags[4 + a.axis]);
+        block_atomic_max(amax, a.amax_out ? a.amax_out + a.axis : &a.flags[4 + a.axis]);
         if (amax > 32767) atomicOr(&a.flags[0], kErrArgRange);   // stored offsets wrapped: unusable
     }
     publish_stats<EPI>(st, a, red);

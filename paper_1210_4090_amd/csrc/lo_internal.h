@@ -127,6 +127,8 @@ struct SweepArgs {
     // events recording its own start and end (lo_time_kernels)
     hipEvent_t ev_start;
     hipEvent_t ev_stop;
+    uint32_t* amax_out;         // argmin sweeps: the step's largest |offset| per axis here (nullptr: flags[4 + a])
+    int wt;                     // fast tiles of 16 lines: outputs written through the L2 (agent-scope stores)
 };
 
 // Launch a sweep kernel K (parenthesised if it has template arguments) with
@@ -188,6 +190,7 @@ struct ScatterArgs {
     int R;
     int C;
     int span;   // R + 2h
+    int wt;     // outputs written through the L2 (a small grid, stores of whole cache lines)
 };
 
 // ---- reverse pass (lo_adjoint.hip) ----
