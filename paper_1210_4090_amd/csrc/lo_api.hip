@@ -130,6 +130,14 @@ uint32_t fold_window(const uint32_t* f, int a)
     return m;
 }
 
+// Largest of kSpread sub-slot words.
+uint32_t fold_spread(const uint32_t* w)
+{
+    uint32_t m = 0;
+    for (int j = 0; j < kSpread; j++) m = std::max(m, w[j]);
+    return m;
+}
+
 // tau K*(s dx / tau) for K(p) = (p + P)^2 / 2, evaluated in a fixed order.
 double mech_cost(int64_t s, double dx, double tau, double P)
 {
@@ -625,7 +633,7 @@ lo_status finish(lo_plan_t p, hipStream_t s, bool argmin)
     p->hflags[0] = f[0];
     for (int a = 0; a < kMaxDim; a++) {
         p->hflags[1 + a] = std::max(p->hflags[1 + a], a < p->ndim ? fold_window(f, a) : 0u);
-        p->hflags[4 + a] = f[4 + a];
+        p->hflags[4 + a] = a < p->ndim ? fold_spread(f + kFlagAmax + a * kSpread) : 0u;
     }
     p->have_diag = true;
     p->had_argmin = argmin;
@@ -1447,7 +1455,7 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
     StreamDrain drain{s};
     const int64_t seg = std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1));
     st = backward_buffers(p, seg, grad_coef != nullptr);
-    if (!st) st = amax_buffer(p, 2 * seg * p->ndim);
+    if (!st) st = amax_buffer(p, 2 * seg * p->ndim * kSpread);
     if (st) return st;
     if (!p->bw_stream) HIPCHK(hipStreamCreateWithFlags(&p->bw_stream, hipStreamNonBlocking));
     for (auto& e : p->bw_ev)
@@ -1466,29 +1474,30 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
     uint32_t hf[8] = {0};
     uint32_t errs = 0;
     std::vector<ScatterArgs> sa[2];
-    std::vector<uint32_t> am((size_t)seg * p->ndim);
+    std::vector<uint32_t> am_raw((size_t)seg * p->ndim * kSpread), am((size_t)seg * p->ndim);
     // Segment k recomputed from its checkpoint (on s2) with every sweep's
     // argmins in buffer k % 2; each step's largest offsets size its scatter
     // tiles.
     auto recompute = [&](int64_t k) -> lo_status {
         const int64_t n0 = k * ckpt_every, n1 = std::min(nsteps, n0 + ckpt_every);
         int16_t* E = p->bw_arg + (size_t)(k % 2) * seg_arg;
-        uint32_t* AM = p->bw_amax + (size_t)(k % 2) * seg * p->ndim;
+        uint32_t* AM = p->bw_amax + (size_t)(k % 2) * seg * p->ndim * kSpread;
         const size_t am_words = (size_t)(n1 - n0) * p->ndim;
         HIPCHK(hipMemcpyAsync(p->bw_u, ckpt + (size_t)k * p->npts, bytes, hipMemcpyDeviceToDevice, s2));
-        HIPCHK(launch_fill_u32(AM, (int64_t)am_words, 0u, s2));
+        HIPCHK(launch_fill_u32(AM, (int64_t)(am_words * kSpread), 0u, s2));
         lo_status r = prologue(p, p->bw_u, n0, s2);
         for (int64_t n = n0; n < n1 && !r; n++) {
             if (n > n0 && (n - n0) % kGraphSteps == 0) r = adapt_from_flags(p, s2);
             if (!r)
                 r = enqueue_step(p, p->bw_u, n, E + (size_t)(n - n0) * p->ndim * p->npts, s2, nullptr,
-                                 AM + (n - n0) * p->ndim);
+                                 AM + (n - n0) * p->ndim * kSpread);
         }
         if (r) return r;
         uint32_t f[kFlagWords];
         HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(f), hipMemcpyDeviceToHost, s2));
-        HIPCHK(hipMemcpyAsync(am.data(), AM, sizeof(uint32_t) * am_words, hipMemcpyDeviceToHost, s2));
+        HIPCHK(hipMemcpyAsync(am_raw.data(), AM, sizeof(uint32_t) * am_words * kSpread, hipMemcpyDeviceToHost, s2));
         HIPCHK(hipStreamSynchronize(s2));
+        for (size_t i = 0; i < am_words; i++) am[i] = fold_spread(am_raw.data() + i * kSpread);
         errs |= f[0];
         if (f[0] & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrArgRange)) return LO_ERR_WINDOW;
         for (int a = 0; a < p->ndim; a++) hf[1 + a] = std::max(hf[1 + a], std::max(p->hflags[1 + a], fold_window(f, a)));
@@ -1582,7 +1591,7 @@ constexpr int64_t kNaTab = 65536 + 64;                 // doubles per axis table
 constexpr int64_t kNaTabPad = 32;                      // and 32 unused doubles on either side
 constexpr int64_t kNaGrid = LO_NOALLOC_MAX_POINTS;     // the second grid array
 constexpr int64_t kNaStats = (int64_t)kSlots * kSlotStride;   // 64-bit words
-constexpr int64_t kNaFlags = 128;                      // doubles: 256 flag words >= kFlagWords
+constexpr int64_t kNaFlags = 256;                      // doubles: 512 flag words >= kFlagWords
 constexpr int64_t kNaWin = 32;                         // doubles: 64 window ints >= 4 kMaxDim
 constexpr int64_t kNaOffGrid = kMaxDim * kNaTab;
 constexpr int64_t kNaOffStats = kNaOffGrid + kNaGrid;

@@ -78,6 +78,16 @@ __device__ inline void block_atomic_max(int v, uint32_t* dst)
     if (threadIdx.x == 0 && s > 0) atomicMax(dst, (uint32_t)s);
 }
 
+// The word of the sub-slots that an argmin sweep's block folds its largest
+// |offset| into: the step's own words when given, else the flags' (spread
+// over kSpread sub-slots, so that the blocks of a launch do not all contend
+// on one address).
+__device__ __forceinline__ uint32_t* amax_word(const SweepArgs& a)
+{
+    const int j = (int)(blockIdx.x % kSpread);
+    return a.amax_out ? a.amax_out + a.axis * kSpread + j : a.flags + kFlagAmax + a.axis * kSpread + j;
+}
+
 // Block-wide max of three values (blockDim <= 512); result in every thread.
 __device__ inline void block_max3(double& a, double& b, double& c, double* red)
 {

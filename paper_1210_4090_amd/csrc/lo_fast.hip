@@ -501,7 +501,7 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
     }
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
     if (ARG && a.argmin) {
-        block_atomic_max(amax, a.amax_out ? a.amax_out + a.axis : &a.flags[4 + a.axis]);
+        block_atomic_max(amax, amax_word(a));
         if (amax > 32767) atomicOr(&a.flags[0], kErrArgRange);   // stored offsets wrapped: unusable
     }
     publish_stats<EPI>(st, a, red);
@@ -718,7 +718,7 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
         emit(std::false_type{});
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
     if (ARG && a.argmin) {
-        block_atomic_max(amax, a.amax_out ? a.amax_out + a.axis : &a.flags[4 + a.axis]);
+        block_atomic_max(amax, amax_word(a));
         if (amax > 32767) atomicOr(&a.flags[0], kErrArgRange);   // stored offsets wrapped: unusable
     }
     publish_stats<EPI>(st, a, red);

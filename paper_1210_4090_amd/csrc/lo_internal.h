@@ -24,10 +24,12 @@ constexpr uint32_t kErrWindowEdge = 2u;   // fixed window: argmin on the edge
 constexpr uint32_t kErrArgRange = 4u;     // argmin offset does not fit int16
 constexpr uint32_t kErrFastPath = 8u;     // fast kernel left a target without a finite candidate
 constexpr uint32_t kErrAdjointHalo = 16u; // reverse pass met an offset beyond its halo (internal error)
-// flags layout: [0] error bits, [4+a] max |argmin|, and the window used by
-// axis a (max over blocks and steps) spread at [kFlagWin + a * kSpread + j]
+// flags layout: [0] error bits; the window used by axis a (max over blocks
+// and steps) spread at [kFlagWin + a * kSpread + j]; the largest |argmin| of
+// axis a (argmin sweeps) spread at [kFlagAmax + a * kSpread + j]
 constexpr int kFlagWin = 8;
-constexpr int kFlagWords = kFlagWin + 3 * kSpread;
+constexpr int kFlagAmax = kFlagWin + 3 * kSpread;
+constexpr int kFlagWords = kFlagAmax + 3 * kSpread;
 
 // Geometry of one axis sweep: a line is the set of points that differ only in
 // coordinate a.  Point (line l, position p) lives at
@@ -127,7 +129,7 @@ struct SweepArgs {
     // events recording its own start and end (lo_time_kernels)
     hipEvent_t ev_start;
     hipEvent_t ev_stop;
-    uint32_t* amax_out;         // argmin sweeps: the step's largest |offset| per axis here (nullptr: flags[4 + a])
+    uint32_t* amax_out;         // argmin sweeps: the step's largest |offset|, [axis][kSpread] (nullptr: the flags')
     int wt;                     // fast tiles of 16 lines: outputs written through the L2 (agent-scope stores)
 };
 

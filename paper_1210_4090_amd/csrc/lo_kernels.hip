@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_row_brute(const double* __restrict__
             __syncthreads();
         }
     }
-    if (ARG && a.argmin) block_atomic_max(amax, a.amax_out ? a.amax_out + a.axis : &a.flags[4 + a.axis]);
+    if (ARG && a.argmin) block_atomic_max(amax, amax_word(a));
     if (a.stats_out) {
         block_max5(sp, sn, sa, shi, snlo, red);
         if (threadIdx.x == 0) {
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_brute(const double* __restrict_
             if (ARG && a.wfix > 0 && (arg[k] <= -wp || arg[k] >= wm)) atomicOr(&a.flags[0], kErrWindowEdge);
         }
     }
-    if (ARG && a.argmin) block_atomic_max(amax, a.amax_out ? a.amax_out + a.axis : &a.flags[4 + a.axis]);
+    if (ARG && a.argmin) block_atomic_max(amax, amax_word(a));
     if (a.stats_out) {
         // forward differences of this sweep's output along the axis
         fv[rr][c] = best[0];
