@@ -70,6 +70,7 @@ constexpr int kCh = 8;           // sources per chunk (tile kernel)
 constexpr int kRowPoints = 2048; // row kernel: points per tile (points per thread x threads)
 constexpr int kTileLines = 16;   // TILE: lines side by side (1 for axes with fewer lines)
 constexpr int kPfTile = 16;      // TILE with the potential step: outputs a thread prefetches tau V for
+constexpr int kPfWide = 4;       // the same for blocks of 512 threads (tiles of 128 targets)
 constexpr double kEps = 1e-6;    // claim widening, in cells
 
 // skewed LDS slot of key x >= 0 for chunks of CH points: one pad slot per
@@ -692,6 +693,11 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
                     bad |= !(x < INFINITY);
                     const double z = x - hvp[i];
                     put<kWt>(dst + off, z);
+                    if (ARG && am) {
+                        const int e = A[t * kKeyStride + c];
+                        am[off] = (int16_t)e;
+                        amax = max(amax, abs(e));
+                    }
                     if (a.stats_out) fold_stats<EPI>(st, x, W[(t + 1) * kKeyStride + c], z);
                 }
                 off += S * (BS / C);
@@ -763,10 +769,11 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
         if (L.C == 1)                                                                                           \
             LO_SWEEP_LAUNCH((K<E, A, 1, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, a, in, out,     \
                             a.kin.k, a, L, inv2c, pofs);                                                        \
-        else if constexpr (E == 1 && A == 0 && B == kBlock) {                                                   \
-            if (a.tile_rows == kPfTile * (kBlock / kTileLines))                                                 \
-                LO_SWEEP_LAUNCH((K<E, A, kTileLines, G, B, kPfTile>), dim3((unsigned)grid, a.nb), dim3(B),      \
-                                lds, s, a, in, out, a.kin.k, a, L, inv2c, pofs);                                \
+        else if constexpr (E == 1) {                                                                            \
+            constexpr int kPf = B == kBlock ? kPfTile : kPfWide;                                                \
+            if (a.tile_rows == kPf * (B / kTileLines))                                                          \
+                LO_SWEEP_LAUNCH((K<E, A, kTileLines, G, B, kPf>), dim3((unsigned)grid, a.nb), dim3(B), lds, s,  \
+                                a, in, out, a.kin.k, a, L, inv2c, pofs);                                        \
             else                                                                                                \
                 LO_SWEEP_LAUNCH((K<E, A, kTileLines, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, a, \
                                 in, out, a.kin.k, a, L, inv2c, pofs);                                           \
