@@ -74,7 +74,8 @@ typedef enum {
                                  steps from there (twice, alternately) and keeps, per axis, one
                                  more than 3% faster than the default; the choice is kept for
                                  later plans of the same grid in the process, and in the file
-                                 named by the environment variable LO_TUNE_CACHE when it is set.
+                                 named by the environment variable LO_TUNE_CACHE when it is set
+                                 (LO_TUNE_LOG, when set, prints each timing to stderr).
                                  Results do not depend on the shape.  lo_effective_H applies
                                  it to each batch. */
 

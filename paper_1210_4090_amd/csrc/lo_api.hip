@@ -854,6 +854,12 @@ lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
                 best.row_ch[a] = alt.row_ch[a];
                 best.tile_fix[a] = alt.tile_fix[a];
             }
+        if (getenv("LO_TUNE_LOG"))
+            for (int a = 0; a < p->ndim; a++)
+                fprintf(stderr, "lo tune %s axis %d: default (%d pts/thread, %d targets) %.4f ms, "
+                        "other (%d, %d) %.4f ms over %d steps -> %s\n", key.c_str(), a, def.row_ch[a],
+                        def.tile_fix[a], ms_def[a], alt.row_ch[a], alt.tile_fix[a], ms_alt[a], kTuneSteps - 1,
+                        best.row_ch[a] == def.row_ch[a] && best.tile_fix[a] == def.tile_fix[a] ? "default" : "other");
         apply_choice(p, best);
         std::lock_guard<std::mutex> lock(g_tune_mutex);
         g_tune_cache.emplace_back(key, best);

@@ -69,8 +69,8 @@ using namespace dev;
 constexpr int kCh = 8;           // sources per chunk (tile kernel)
 constexpr int kRowPoints = 2048; // row kernel: points per tile (points per thread x threads)
 constexpr int kTileLines = 16;   // TILE: lines side by side (1 for axes with fewer lines)
-constexpr int kPfTile = 16;      // TILE with the potential step: outputs a thread prefetches tau V for
-constexpr int kPfWide = 4;       // the same for blocks of 512 threads (tiles of 128 targets)
+// TILE with the potential step: each thread prefetches tau V for its R / (BS / 16)
+// outputs (16 or 8 in blocks of 256 threads, 4 or 8 in blocks of 512 threads)
 constexpr double kEps = 1e-6;    // claim widening, in cells
 
 // skewed LDS slot of key x >= 0 for chunks of CH points: one pad slot per
@@ -770,9 +770,12 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
             LO_SWEEP_LAUNCH((K<E, A, 1, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, a, in, out,     \
                             a.kin.k, a, L, inv2c, pofs);                                                        \
         else if constexpr (E == 1) {                                                                            \
-            constexpr int kPf = B == kBlock ? kPfTile : kPfWide;                                                \
-            if (a.tile_rows == kPf * (B / kTileLines))                                                          \
-                LO_SWEEP_LAUNCH((K<E, A, kTileLines, G, B, kPf>), dim3((unsigned)grid, a.nb), dim3(B), lds, s,  \
+            constexpr int kPfA = B == kBlock ? 16 : 4, kPfB = 8;                                                \
+            if (a.tile_rows == kPfA * (B / kTileLines))                                                         \
+                LO_SWEEP_LAUNCH((K<E, A, kTileLines, G, B, kPfA>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, \
+                                a, in, out, a.kin.k, a, L, inv2c, pofs);                                        \
+            else if (a.tile_rows == kPfB * (B / kTileLines))                                                    \
+                LO_SWEEP_LAUNCH((K<E, A, kTileLines, G, B, kPfB>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, \
                                 a, in, out, a.kin.k, a, L, inv2c, pofs);                                        \
             else                                                                                                \
                 LO_SWEEP_LAUNCH((K<E, A, kTileLines, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, a, \
