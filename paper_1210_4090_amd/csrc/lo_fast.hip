@@ -403,22 +403,35 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
             __syncthreads();   // keys are reused by the next tile
         }
     } else {
+        // this thread's sources of a tile: points p0 - 1 .. p0 + CH of its row
+        auto load_src = [&](int64_t tile, double (&v)[CH + 2]) {
+            const int64_t row = tile * nr + r;
+            if (act && row < a.g.nlines) {
+                const double* __restrict__ q = in + row * N;
+                v[0] = q[p0 == 0 ? N - 1 : p0 - 1];
+                const double2* q2 = (const double2*)(q + p0);
+#pragma unroll
+                for (int k = 0; k < CH / 2; k++) {
+                    const double2 w = q2[k];
+                    v[1 + 2 * k] = w.x;
+                    v[2 + 2 * k] = w.y;
+                }
+                v[CH + 1] = q[p0 + CH == N ? 0 : p0 + CH];
+            }
+        };
+        // 8 points a thread: a block's next tile's sources are loaded right
+        // after the claims of its current one, so that their latency passes
+        // during the emit (2048^2 row sweep 19.8 -> 19.3 us; with 4 points a
+        // thread, twice the waves already hide it, and the 3-D and batched
+        // row sweeps got 2-4% slower)
+        constexpr bool kNextSrc = CH == 8;
+        double uu[CH + 2];
+        if (kNextSrc && blockIdx.x < ntiles) load_src(blockIdx.x, uu);
         for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
             const int64_t row = tile * nr + r;
             const bool ok = act && row < a.g.nlines;
             const double* __restrict__ src = in + row * N;
-            double uu[CH + 2];
-            if (ok) {
-                uu[0] = src[p0 == 0 ? N - 1 : p0 - 1];
-                const double2* s2 = (const double2*)(src + p0);
-#pragma unroll
-                for (int k = 0; k < CH / 2; k++) {
-                    const double2 v = s2[k];
-                    uu[1 + 2 * k] = v.x;
-                    uu[2 + 2 * k] = v.y;
-                }
-                uu[CH + 1] = src[p0 + CH == N ? 0 : p0 + CH];
-            }
+            if (!kNextSrc) load_src(tile, uu);
             if (ok) {
 #pragma unroll
                 for (int k = 0; k < CH; k++) {
@@ -461,6 +474,8 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
                 }
                 __syncthreads();
             }
+            double un[CH + 2];
+            if (kNextSrc && tile + gridDim.x < ntiles) load_src(tile + gridDim.x, un);
             if (ok) {
                 double x[CH + 1];
 #pragma unroll
@@ -498,6 +513,9 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
                 }
             }
             __syncthreads();   // keys are reused by the next tile
+            if (kNextSrc)
+#pragma unroll
+                for (int k = 0; k < CH + 2; k++) uu[k] = un[k];
         }
     }
     if (bad) atomicOr(&a.flags[0], kErrFastPath);
@@ -616,10 +634,27 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
     const double gsl = a.kslack;
     __syncthreads();
 
-    if (fast) {
-        // sources that can reach the targets: [r0 - wp, r0 + NT - 1 + wm]
+    // sources that can reach the targets: [r0 - wp, r0 + NT - 1 + wm]
+    const int nch_fast = (NT - 1 + wm + wp + kCh) / kCh;
+    if (ARG && fast && nch_fast <= BS / C) {
+        // at most one chunk a thread: its sources stay in registers for the
+        // second pass
         const int pA = r0 - wp, pB = r0 + NT - 1 + wm;
-        const int nch = (pB - pA + kCh) / kCh;
+        const int p0 = pA + q * kCh;
+        const bool has = q < nch_fast && lok;
+        double uu[kCh + 2];
+        auto key = [r0](int t) { return (t - r0) * kKeyStride; };
+        if (has) {
+            load_chunk(p0, uu);
+            claim_chunk<0, kCh, GEN>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, gsl, W + c, A + c, key);
+        }
+        __syncthreads();
+        if (has)
+            claim_chunk<1, kCh, GEN>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, gsl, W + c, A + c, key);
+        __syncthreads();
+    } else if (fast) {
+        const int pA = r0 - wp, pB = r0 + NT - 1 + wm;
+        const int nch = nch_fast;
         for (int pass = 0; pass < (ARG ? 2 : 1); pass++) {
             for (int ch = q; ch < nch && lok; ch += BS / C) {
                 const int p0 = pA + ch * kCh;
