@@ -443,3 +443,28 @@ np.save(sys.argv[1], u.cpu().numpy())
         lines = cache.read_text().splitlines()
         assert len(lines) == 1 and "|" in lines[0], lines
     assert np.array_equal(np.load(str(out) % 1), np.load(str(out) % 2))
+
+
+@pytest.mark.parametrize("n, n1", [(256, 64), (2048, 1280)])
+def test_row_argmins_into_an_unaligned_buffer(torch_dev, n, n1):
+    """Row sweeps store a thread's consecutive offsets with one wide store
+    where the caller's buffer is aligned for it, one by one otherwise: a
+    buffer that starts 2 bytes past an aligned address receives the same
+    offsets (256 x 64: few tiles, 4 points a thread; 2048 x 1280: 8)."""
+    torch = torch_dev
+    import ctypes
+    from paper_1210_4090_amd._lib import check, lib
+    w = wl.config2(n, n1=n1)
+    print_case("unaligned argmins", n, n1)
+    p = _plan(torch, w.n, w.tau, w.P, V=w.V, method="fast")
+    u0 = _gpu(torch, w.u0)
+    u1 = u0.clone()
+    ref = p.step(u1, 0, argmin=True)
+    big = torch.zeros(ref.numel() + 8, dtype=torch.int16, device="cuda")
+    E = big[1:1 + ref.numel()].view(ref.shape)
+    assert E.data_ptr() % 16 == 2
+    u2 = u0.clone()
+    check("lo_step", lib().lo_step(p._h, ctypes.c_void_p(u2.data_ptr()), 0, ctypes.c_void_p(E.data_ptr()), None))
+    torch.cuda.synchronize()
+    assert torch.equal(u1, u2)
+    assert torch.equal(E, ref), int((E != ref).sum())
