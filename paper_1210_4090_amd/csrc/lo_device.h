@@ -320,7 +320,10 @@ __device__ inline void next_windows(const WinParams& Pg, int64_t inst, const uin
     constexpr int kParamWords = (int)(sizeof(WinParams) / 8);
     static_assert(sizeof(WinParams) % 8 == 0 && kParamWords <= kWave, "one wave copies the parameters");
     __shared__ double sw[kWords];
-    __shared__ uint64_t spw[kParamWords];
+    __shared__ union {
+        WinParams p;
+        uint64_t w[kParamWords];
+    } sp;
     __shared__ int part[kMaxDim][4];
     __shared__ int caps[kMaxDim][4];
     const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, nwv = blockDim.x / kWave;
@@ -332,7 +335,7 @@ __device__ inline void next_windows(const WinParams& Pg, int64_t inst, const uin
             v[i] = k < kWords ? slot[k * kSpread + lane] : 0;
         }
         uint64_t pw = 0;
-        if (w == 0 && lane < kParamWords) pw = ((const uint64_t*)&Pg)[lane];
+        if (w == 0 && lane < kParamWords) __builtin_memcpy(&pw, (const char*)&Pg + 8 * lane, 8);
 #pragma unroll
         for (int i = 0; i < 3; i++) {
             const int k = w + i * nwv;
@@ -341,10 +344,10 @@ __device__ inline void next_windows(const WinParams& Pg, int64_t inst, const uin
                 if (lane == kWave - 1) sw[k] = m;
             }
         }
-        if (w == 0 && lane < kParamWords) spw[lane] = pw;
+        if (w == 0 && lane < kParamWords) sp.w[lane] = pw;
     }
     __syncthreads();
-    const WinParams& P = *(const WinParams*)spw;
+    const WinParams& P = sp.p;
     const double M = sw[6] + (P.lag ? P.slack_extra : 0.0);
     const double osc0 = sw[7] + sw[8] + (P.lag ? P.hv_osc : 0.0);
     for (int t = w; t < 4 * P.ndim; t += nwv) {

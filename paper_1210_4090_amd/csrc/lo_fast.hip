@@ -154,7 +154,7 @@ __device__ __forceinline__ int table_cross(const double* K, int sl, int sh, doub
 // over the staged differences, with the comparison widened by
 // gsl + 2^-40 (|u(j)| + |u(j+1)|), far above the rounding of the candidates,
 // so that every minimiser (ties included) stays among the claimants.
-template <int PASS, int CH, bool GEN, typename KeyOf>
+template <int PASS, int CH, bool GEN, typename KeyOf, bool U2 = false>
 __device__ __forceinline__ void claim_chunk(const double (&uu)[CH + 2], int p0, int plast, int tmin, int tmax,
                                             int smin, int smax, const double* K, double inv2c, double pofs,
                                             double gsl, double* W, int* A, KeyOf key)
@@ -182,6 +182,13 @@ __device__ __forceinline__ void claim_chunk(const double (&uu)[CH + 2], int p0, 
             jh += 1.0;
         }
     }
+    auto claim = [&](int p, int t, double v) {
+        const int s = key(t);
+        if (PASS == 0)
+            atomicMin(&W[s], v);
+        else if (v == W[s])
+            atomicMin(&A[s], p - t);
+    };
 #pragma unroll
     for (int k = 0; k < CH; k++) {
         const int p = p0 + k;
@@ -189,13 +196,16 @@ __device__ __forceinline__ void claim_chunk(const double (&uu)[CH + 2], int p0, 
         const int tlo = max(max(lo[k], p + smin - 1), tmin - 1) + 1;
         const int thi = min(min(hi[k + 1], p + smax), tmax);
         const double up = uu[k + 1];
-        for (int t = tlo; t <= thi; t++) {
-            const double v = up + K[t - p];
-            const int s = key(t);
-            if (PASS == 0)
-                atomicMin(&W[s], v);
-            else if (v == W[s])
-                atomicMin(&A[s], p - t);
+        if (U2 && tlo <= thi) {
+            // U2: a source claims one or two targets in the common case: both
+            // costs are read at once (the second lies in the staged band, or
+            // is the word just past it when tlo = thi), the rest in a loop
+            const double k0 = K[tlo - p], k1 = K[tlo + 1 - p];
+            claim(p, tlo, up + k0);
+            if (tlo < thi) claim(p, tlo + 1, up + k1);
+            for (int t = tlo + 2; t <= thi; t++) claim(p, t, up + K[t - p]);
+        } else if (!U2) {
+            for (int t = tlo; t <= thi; t++) claim(p, t, up + K[t - p]);
         }
     }
 }
@@ -442,13 +452,13 @@ k_claim_row(const double* __restrict__ in, double* __restrict__ out, const doubl
             __syncthreads();
             if (fast) {
                 if (ok)
-                    claim_chunk<0, CH, GEN>(uu, p0, N - 1, smin, N - 1 + smax, smin, smax, K, inv2c, pofs, gsl, W, A,
-                                            key);
+                    claim_chunk<0, CH, GEN, decltype(key), ARG>(uu, p0, N - 1, smin, N - 1 + smax, smin, smax, K,
+                                                                inv2c, pofs, gsl, W, A, key);
                 __syncthreads();
                 if (ARG) {
                     if (ok)
-                        claim_chunk<1, CH, GEN>(uu, p0, N - 1, smin, N - 1 + smax, smin, smax, K, inv2c, pofs, gsl,
-                                                W, A, key);
+                        claim_chunk<1, CH, GEN, decltype(key), ARG>(uu, p0, N - 1, smin, N - 1 + smax, smin, smax, K,
+                                                                    inv2c, pofs, gsl, W, A, key);
                     __syncthreads();
                 }
             } else {
@@ -550,6 +560,10 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
         if (a.pofs_b) pofs = a.pofs;
     }
     constexpr int kKeyStride = tile_key_stride(C);
+    // the first two claims of a source unrolled: faster in blocks of 512
+    // threads of 16-line tiles (few tiles) and in argmin sweeps; slower in the
+    // 3-D tile sweeps and in one-line tiles
+    constexpr bool kU2 = (C == kTileLines && BS == 512) || ARG;
     const int N = (int)a.g.n;
     const int S = (int)a.g.stride;   // line offsets fit 32 bits (the plan caps the grid at 2^31 points)
     const int R = a.tile_rows;
@@ -646,11 +660,13 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
         auto key = [r0](int t) { return (t - r0) * kKeyStride; };
         if (has) {
             load_chunk(p0, uu);
-            claim_chunk<0, kCh, GEN>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, gsl, W + c, A + c, key);
+            claim_chunk<0, kCh, GEN, decltype(key), true>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, gsl,
+                                                          W + c, A + c, key);
         }
         __syncthreads();
         if (has)
-            claim_chunk<1, kCh, GEN>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, gsl, W + c, A + c, key);
+            claim_chunk<1, kCh, GEN, decltype(key), true>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, gsl,
+                                                          W + c, A + c, key);
         __syncthreads();
     } else if (fast) {
         const int pA = r0 - wp, pB = r0 + NT - 1 + wm;
@@ -662,11 +678,11 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
                 load_chunk(p0, uu);
                 auto key = [r0](int t) { return (t - r0) * kKeyStride; };
                 if (pass == 0)
-                    claim_chunk<0, kCh, GEN>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, gsl, W + c,
-                                             A + c, key);
+                    claim_chunk<0, kCh, GEN, decltype(key), kU2>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c,
+                                                                 pofs, gsl, W + c, A + c, key);
                 else
-                    claim_chunk<1, kCh, GEN>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c, pofs, gsl, W + c,
-                                             A + c, key);
+                    claim_chunk<1, kCh, GEN, decltype(key), kU2>(uu, p0, pB, r0, r0 + NT - 1, smin, smax, K, inv2c,
+                                                                 pofs, gsl, W + c, A + c, key);
             }
             __syncthreads();
         }
