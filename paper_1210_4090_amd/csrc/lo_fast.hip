@@ -28,9 +28,12 @@
 //
 // A minimiser lies within the step's window, so claims are clipped to it; a
 // clipped candidate is never the minimum.  Costs come from a band of 2 KH + 1
-// consecutive offsets of the table staged in LDS (KH is the plan's halo),
-// starting at the window's low end, so an asymmetric window (a large |P|
-// shifts the minimisers) fits whenever its width does.  A wider window is
+// consecutive offsets of the table staged in LDS, centred on the cost's
+// vertex (P tau / dx for the mechanical cost, a caller table's minimising
+// offset), which is known before the window is read, so the band's loads go
+// out first.  A large |P| shifts the minimisers, and the window with them,
+// towards the vertex's side; KH (the plan's halo plus the vertex's distance
+// from 0) then covers the window whenever its width fits.  A wider window is
 // claimed band by band, restaging the table between bands (minima over the
 // union of the candidates are the same), in chunks of two sources so that
 // this rare path needs fewer registers than the main one.  The kept value is
