@@ -70,8 +70,10 @@ typedef enum {
 #define LO_FLAG_NO_GRAPH 1u   /* lo_run: launch kernels directly, no HIP graph */
 #define LO_FLAG_AUTOTUNE 2u   /* LO_FAST: the first lo_run advances a copy of its input 60 steps
                                  (past the wide windows of the first steps), times each fast
-                                 sweep's launch shapes (tile length, points per thread) over 8
-                                 steps from there (twice, alternately) and keeps, per axis, one
+                                 sweep's launch shapes (points per thread of a row sweep, tile
+                                 length of the last axis's tile sweep; other tile axes keep a
+                                 length that follows the window) over 8 steps from there
+                                 (twice, alternately) and keeps, per axis, one
                                  more than 3% faster than the default; the choice is kept for
                                  later plans of the same grid in the process, and in the file
                                  named by the environment variable LO_TUNE_CACHE when it is set

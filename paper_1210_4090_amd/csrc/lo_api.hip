@@ -682,7 +682,8 @@ lo_status amax_buffer(lo_plan_t p, int64_t words)
 
 // Launch-shape tuner (LO_FLAG_AUTOTUNE).  The shapes: points per thread of a
 // row sweep (8, or 4 with blocks of twice the threads) and targets per tile of
-// a tile sweep (256 or 128).  Every shape computes the same values (the
+// the last axis's tile sweep (256 or 128; other tile axes keep their default,
+// which follows the window during the run).  Every shape computes the same values (the
 // minimum over a target's claimants does not depend on how sources are
 // grouped), so the choice only affects speed.
 //  - Steady state: the windows of the first steps of a run from smooth data
@@ -830,9 +831,13 @@ lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
     for (int a = 0; a < kMaxDim; a++) {
         def.row_ch[a] = a < p->ndim ? p->row_ch[a] : 8;
         alt.row_ch[a] = 12 - def.row_ch[a];
-        const bool wide = a < p->ndim && (p->halo[a] >= 40 || a == p->ndim - 1);
-        def.tile_fix[a] = a < p->ndim && p->kind[a] == kKindTile ? tile_len(p, a, wide) : 0;
-        alt.tile_fix[a] = a < p->ndim && p->kind[a] == kKindTile ? tile_len(p, a, !wide) : 0;
+        // tile lengths: the last axis (fixed at the longer tiles by default)
+        // is tuned; the others keep their default, which follows the window
+        // (long tiles while it is wide, short ones after), a better schedule
+        // over a run than any one length timed from one state
+        const bool last = a == p->ndim - 1;
+        def.tile_fix[a] = last && p->kind[a] == kKindTile ? tile_len(p, a, true) : 0;
+        alt.tile_fix[a] = last && p->kind[a] == kKindTile ? tile_len(p, a, false) : 0;
     }
     {
         // two rounds, alternating the shapes; the faster round of each counts
