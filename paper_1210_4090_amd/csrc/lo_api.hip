@@ -95,6 +95,11 @@ struct lo_plan_s {
     uint32_t* bw_err = nullptr;      // error bits of the reverse sweeps
     uint32_t* bw_amax = nullptr;     // largest |offset| of every (step, axis) whose scatter follows
     int64_t bw_amax_words = 0;
+    // pinned host words for the read-backs of flags and offsets during a run:
+    // a copy into pageable memory is staged by the runtime, which held back
+    // the reverse pass's recompute stream until the other stream had drained
+    uint32_t* hpin = nullptr;
+    size_t hpin_words = 0;
     hipStream_t bw_stream = nullptr; // lo_backward: segment recomputes, beside the reverse sweeps
     hipEvent_t bw_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // start, recomputed[2], reversed[2]
     double* bw_part = nullptr;       // projection partial sums [nmodes][blocks] + [nmodes]
@@ -187,6 +192,7 @@ void free_plan(lo_plan_t p)
     if (p->bw_arg) (void)hipFree(p->bw_arg);
     if (p->bw_err) (void)hipFree(p->bw_err);
     if (p->bw_amax) (void)hipFree(p->bw_amax);
+    if (p->hpin) (void)hipHostFree(p->hpin);
     for (auto& e : p->bw_ev)
         if (e) (void)hipEventDestroy(e);
     if (p->bw_stream) (void)hipStreamDestroy(p->bw_stream);
@@ -506,10 +512,27 @@ int choose_halo(lo_plan_t p, int a, int W)
 }
 
 // Halos from the widest window the kernels used since the last call.
+// At least `words` pinned host words (nullptr if they cannot be had).
+uint32_t* host_words(lo_plan_t p, size_t words)
+{
+    if (words > p->hpin_words) {
+        if (p->hpin) (void)hipHostFree(p->hpin);
+        p->hpin = nullptr;
+        p->hpin_words = 0;
+        if (hipHostMalloc((void**)&p->hpin, sizeof(uint32_t) * words, hipHostMallocDefault) != hipSuccess) {
+            p->hpin = nullptr;
+            return nullptr;
+        }
+        p->hpin_words = words;
+    }
+    return p->hpin;
+}
+
 lo_status adapt_from_flags(lo_plan_t p, hipStream_t s)
 {
-    uint32_t f[kFlagWords];
-    HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(f), hipMemcpyDeviceToHost, s));
+    uint32_t* f = host_words(p, kFlagWords);
+    if (!f) return LO_ERR_HIP;
+    HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(uint32_t) * kFlagWords, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int a = 0; a < p->ndim; a++) {
         const uint32_t wu = fold_window(f, a);
@@ -1485,7 +1508,7 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
     uint32_t hf[8] = {0};
     uint32_t errs = 0;
     std::vector<ScatterArgs> sa[2];
-    std::vector<uint32_t> am_raw((size_t)seg * p->ndim * kSpread), am((size_t)seg * p->ndim);
+    std::vector<uint32_t> am((size_t)seg * p->ndim);
     // Segment k recomputed from its checkpoint (on s2) with every sweep's
     // argmins in buffer k % 2; each step's largest offsets size its scatter
     // tiles.
@@ -1504,11 +1527,13 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
                                  AM + (n - n0) * p->ndim * kSpread);
         }
         if (r) return r;
-        uint32_t f[kFlagWords];
-        HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(f), hipMemcpyDeviceToHost, s2));
-        HIPCHK(hipMemcpyAsync(am_raw.data(), AM, sizeof(uint32_t) * am_words * kSpread, hipMemcpyDeviceToHost, s2));
+        uint32_t* f = host_words(p, kFlagWords + am_words * kSpread);
+        if (!f) return LO_ERR_HIP;
+        uint32_t* am_raw = f + kFlagWords;
+        HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(uint32_t) * kFlagWords, hipMemcpyDeviceToHost, s2));
+        HIPCHK(hipMemcpyAsync(am_raw, AM, sizeof(uint32_t) * am_words * kSpread, hipMemcpyDeviceToHost, s2));
         HIPCHK(hipStreamSynchronize(s2));
-        for (size_t i = 0; i < am_words; i++) am[i] = fold_spread(am_raw.data() + i * kSpread);
+        for (size_t i = 0; i < am_words; i++) am[i] = fold_spread(am_raw + i * kSpread);
         errs |= f[0];
         if (f[0] & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrArgRange)) return LO_ERR_WINDOW;
         for (int a = 0; a < p->ndim; a++) hf[1 + a] = std::max(hf[1 + a], std::max(p->hflags[1 + a], fold_window(f, a)));
