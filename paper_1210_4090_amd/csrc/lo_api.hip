@@ -100,6 +100,7 @@ struct lo_plan_s {
     // the reverse pass's recompute stream until the other stream had drained
     uint32_t* hpin = nullptr;
     size_t hpin_words = 0;
+    bool narrow = false;             // sweeps at one block a CU (the reverse pass's recompute)
     hipStream_t bw_stream = nullptr; // lo_backward: segment recomputes, beside the reverse sweeps
     hipEvent_t bw_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // start, recomputed[2], reversed[2]
     double* bw_part = nullptr;       // projection partial sums [nmodes][blocks] + [nmodes]
@@ -604,6 +605,7 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
         // little to write back (a larger grid's dirty lines leave the caches
         // during the sweep anyway, and writing through costs it time)
         A.wt = p->npts * p->nb <= ((int64_t)1 << 22) ? 1 : 0;
+        A.narrow = p->narrow ? 1 : 0;
         A.quad = p->user_table[a] ? 0 : 1;
         A.cq = p->dx[a] * p->dx[a] / (2.0 * p->d.tau);
         A.inv2c = 1.0 / (2.0 * A.cq);
@@ -1520,12 +1522,16 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
         HIPCHK(hipMemcpyAsync(p->bw_u, ckpt + (size_t)k * p->npts, bytes, hipMemcpyDeviceToDevice, s2));
         HIPCHK(launch_fill_u32(AM, (int64_t)(am_words * kSpread), 0u, s2));
         lo_status r = prologue(p, p->bw_u, n0, s2);
+        // every recompute but the first runs beside the scatters of the segment
+        // after it: its sweeps leave room for them on every CU
+        p->narrow = n1 < nsteps;
         for (int64_t n = n0; n < n1 && !r; n++) {
             if (n > n0 && (n - n0) % kGraphSteps == 0) r = adapt_from_flags(p, s2);
             if (!r)
                 r = enqueue_step(p, p->bw_u, n, E + (size_t)(n - n0) * p->ndim * p->npts, s2, nullptr,
                                  AM + (n - n0) * p->ndim * kSpread);
         }
+        p->narrow = false;
         if (r) return r;
         uint32_t* f = host_words(p, kFlagWords + am_words * kSpread);
         if (!f) return LO_ERR_HIP;

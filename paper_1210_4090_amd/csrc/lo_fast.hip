@@ -910,18 +910,25 @@ hipError_t launch_fast(const double* in, double* out, const SweepArgs& a, double
     int64_t tiles = a.kind == kKindRow
                         ? (a.g.nlines + nr - 1) / nr
                         : ((a.g.n + a.tile_rows - 1) / a.tile_rows) * ((a.g.nlines + C - 1) / C);
-    const bool few = tiles * a.nb * 2 <= a.grid_cap;
+    // narrow: blocks of 512 threads, rows walked by one block a CU and tiles
+    // of 16 lines x 256 targets, so that the sweep leaves room on every CU for
+    // the blocks of a kernel on another stream
+    const bool narrow = a.narrow != 0;
+    const bool few = narrow || tiles * a.nb * 2 <= a.grid_cap;
     const int row_ch = a.row_ch == 4 || (few && a.kind == kKindRow) ? 4 : 8;
     SweepArgs b = a;
     b.row_ch = row_ch;
-    if (few && a.kind == kKindTile && C == kTileLines && a.tile_rows > 128) {
+    if (narrow && a.kind == kKindTile && C == kTileLines) {
+        b.tile_rows = 256;
+        tiles = ((a.g.n + 255) / 256) * ((a.g.nlines + C - 1) / C);
+    } else if (few && a.kind == kKindTile && C == kTileLines && a.tile_rows > 128) {
         b.tile_rows = 128;
         tiles = ((a.g.n + 127) / 128) * ((a.g.nlines + C - 1) / C);
     }
     const ClaimLds L = claim_layout(a.kind, a.g.n, b.tile_rows, a.halo, arg, row_ch, C);
     // ROW: persistent blocks, about grid_cap in all (instances included), each
     // walking several tiles so that its fixed costs are amortised
-    const int64_t cap = std::max(1, a.grid_cap / std::max(1, a.nb));
+    const int64_t cap = std::max(1, (narrow ? a.grid_cap / 4 : a.grid_cap) / std::max(1, a.nb));
     if (a.kind == kKindRow) return launch_claim_t<1>(in, out, b, L, inv2c, pofs, std::min(tiles, cap), false, s);
     return launch_claim_t<0>(in, out, b, L, inv2c, pofs, tiles, few, s);
 }

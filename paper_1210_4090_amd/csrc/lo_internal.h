@@ -131,6 +131,7 @@ struct SweepArgs {
     hipEvent_t ev_stop;
     uint32_t* amax_out;         // argmin sweeps: the step's largest |offset|, [axis][kSpread] (nullptr: the flags')
     int wt;                     // fast tiles of 16 lines: outputs written through the L2 (agent-scope stores)
+    int narrow;                 // fast sweeps at one 512-thread block a CU (room for another stream's kernels)
 };
 
 // Launch a sweep kernel K (parenthesised if it has template arguments) with
