@@ -562,6 +562,17 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
         kc += ko;
         if (a.pofs_b) pofs = a.pofs;
     }
+    // one-line tiles: a search block (block 0, dispatched first) only
+    // computes the next step's windows, from statistics complete before the
+    // launch, beside the tiles, which go to blocks 1, 2, ...  (In the row
+    // sweeps, whose search block would have to share the start of the
+    // launch with every tile's loads, it gained nothing.)
+    const int sbk = C == 1 ? a.search_block : 0;
+    if (sbk && blockIdx.x == 0) {
+        clear_slot(a.stats_clear);
+        maybe_next_windows(a);
+        return;
+    }
     constexpr int kKeyStride = tile_key_stride(C);
     // the first two claims of a source unrolled: faster in blocks of 512
     // threads of 16-line tiles (few tiles) and in argmin sweeps; slower in the
@@ -574,7 +585,7 @@ __global__ __launch_bounds__(BS) void k_claim_tile(const double* __restrict__ in
     // block, tile and line indices fit 32 bits (the plan caps the grid at 2^31 points)
     const int nTB = (N + R - 1) / R;
     const int nLB = (int)((a.g.nlines + C - 1) / C);
-    const int b = (int)remap_block(blockIdx.x, (int64_t)nTB * nLB);
+    const int b = (int)remap_block(blockIdx.x - sbk, (int64_t)nTB * nLB);
     const int lb = b / nTB;
     const int r0 = (b - lb * nTB) * R;
     const int Rt = min(R, N - r0);
@@ -811,6 +822,22 @@ ClaimLds claim_layout(int kind, int64_t N, int tile_rows, int H, bool arg, int r
     return L;
 }
 
+// Whether a launch of `grid` blocks (per instance) that computes the next
+// step's windows can give them a block of its own: when one more block is
+// resident at once, so that no tile waits for the search block's slot.
+template <typename Kern>
+bool search_block_fits(Kern k, int bs, size_t lds, int64_t grid, const SweepArgs& a)
+{
+    if (!a.win_next) return false;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, bs, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const int64_t ncu = a.grid_cap / 4;   // plans size grid_cap at four blocks a compute unit
+    return (grid + 1) * std::max(1, a.nb) <= (int64_t)per_cu * ncu;
+}
+
 template <int ROW>
 hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, const ClaimLds& L, double inv2c,
                           double pofs, int64_t grid, bool wide, hipStream_t s)
@@ -820,10 +847,12 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
     const bool epi = a.hv != nullptr;
 #define LO_CLAIM_LAUNCH_B(K, E, A, G, B)                                                                       \
     do {                                                                                                        \
-        if (L.C == 1)                                                                                           \
-            LO_SWEEP_LAUNCH((K<E, A, 1, G, B, 0>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, a, in, out,     \
-                            a.kin.k, a, L, inv2c, pofs);                                                        \
-        else if constexpr (E == 1) {                                                                            \
+        if (L.C == 1) {                                                                                         \
+            SweepArgs c = a;                                                                                    \
+            c.search_block = search_block_fits(K<E, A, 1, G, B, 0>, B, lds, grid, a) ? 1 : 0;                   \
+            LO_SWEEP_LAUNCH((K<E, A, 1, G, B, 0>), dim3((unsigned)(grid + c.search_block), a.nb), dim3(B), lds, \
+                            s, a, in, out, a.kin.k, c, L, inv2c, pofs);                                         \
+        } else if constexpr (E == 1) {                                                                            \
             constexpr int kPfA = B == kBlock ? 16 : 4, kPfB = 8;                                                \
             if (a.tile_rows == kPfA * (B / kTileLines))                                                         \
                 LO_SWEEP_LAUNCH((K<E, A, kTileLines, G, B, kPfA>), dim3((unsigned)grid, a.nb), dim3(B), lds, s, \

@@ -131,7 +131,9 @@ struct SweepArgs {
     hipEvent_t ev_stop;
     uint32_t* amax_out;         // argmin sweeps: the step's largest |offset|, [axis][kSpread] (nullptr: the flags')
     int wt;                     // fast tiles of 16 lines: outputs written through the L2 (agent-scope stores)
-    int narrow;                 // fast sweeps at one 512-thread block a CU (room for another stream's kernels)
+    int16_t narrow;             // fast sweeps at one 512-thread block a CU (room for another stream's kernels)
+    int16_t search_block;       // fast one-line tile sweeps: block 0 only computes the next step's windows,
+                                // the sweep's tiles go to blocks 1, 2, ... (set by the launcher)
 };
 
 // Launch a sweep kernel K (parenthesised if it has template arguments) with
