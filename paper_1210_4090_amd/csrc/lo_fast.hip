@@ -845,13 +845,24 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
     const size_t lds = claim_lds_bytes(L);
     const bool arg = a.argmin != nullptr;
     const bool epi = a.hv != nullptr;
+    // one-line tiles (with the potential step: tau V prefetched for tiles of
+    // 2 or 4 targets a thread), with a search block when one fits
+#define LO_LINE_LAUNCH(K, E, A, G, B, PF)                                                                      \
+    do {                                                                                                        \
+        SweepArgs c = a;                                                                                        \
+        c.search_block = search_block_fits(K<E, A, 1, G, B, PF>, B, lds, grid, a) ? 1 : 0;                      \
+        LO_SWEEP_LAUNCH((K<E, A, 1, G, B, PF>), dim3((unsigned)(grid + c.search_block), a.nb), dim3(B), lds, s, \
+                        a, in, out, a.kin.k, c, L, inv2c, pofs);                                                \
+    } while (0)
 #define LO_CLAIM_LAUNCH_B(K, E, A, G, B)                                                                       \
     do {                                                                                                        \
         if (L.C == 1) {                                                                                         \
-            SweepArgs c = a;                                                                                    \
-            c.search_block = search_block_fits(K<E, A, 1, G, B, 0>, B, lds, grid, a) ? 1 : 0;                   \
-            LO_SWEEP_LAUNCH((K<E, A, 1, G, B, 0>), dim3((unsigned)(grid + c.search_block), a.nb), dim3(B), lds, \
-                            s, a, in, out, a.kin.k, c, L, inv2c, pofs);                                         \
+            if constexpr (E == 1) {                                                                             \
+                if (a.tile_rows == 2 * B) LO_LINE_LAUNCH(K, E, A, G, B, 2);                                     \
+                else if (a.tile_rows == 4 * B) LO_LINE_LAUNCH(K, E, A, G, B, 4);                                \
+                else LO_LINE_LAUNCH(K, E, A, G, B, 0);                                                          \
+            } else                                                                                              \
+                LO_LINE_LAUNCH(K, E, A, G, B, 0);                                                               \
         } else if constexpr (E == 1) {                                                                            \
             constexpr int kPfA = B == kBlock ? 16 : 4, kPfB = 8;                                                \
             if (a.tile_rows == kPfA * (B / kTileLines))                                                         \
@@ -910,6 +921,7 @@ hipError_t launch_claim_t(const double* in, double* out, const SweepArgs& a, con
 #undef LO_CLAIM_LAUNCH
 #undef LO_CLAIM_LAUNCH_G
 #undef LO_CLAIM_LAUNCH_B
+#undef LO_LINE_LAUNCH
 #undef LO_ROW_LAUNCH
 #undef LO_ROW_LAUNCH_CH
 #undef LO_ROW_LAUNCH_G
