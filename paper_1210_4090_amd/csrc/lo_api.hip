@@ -44,7 +44,7 @@ struct lo_plan_s {
     int tile_fix[kMaxDim] = {0, 0, 0};    // fast tiles: length chosen by the tuner (0: from the halo)
     int row_ch[kMaxDim] = {8, 8, 8};      // fast rows: points per thread
     bool tuned = false;
-    double* tune_u = nullptr;             // the tuner's copy of the input
+    double* tune_u = nullptr;             // the tuner's copy of the input (while it runs)
     bool fast[kMaxDim] = {false, false, false};
     // potential
     int nmodes = 0;
@@ -842,10 +842,18 @@ lo_status autotune(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
         if (adv) (void)hipFree(adv);
         return st;
     }
+    // both buffers are the tuner's own: freed when it returns (after its
+    // final synchronisation), so that a tuned plan holds what a default one does
     struct Free {
         double* q;
-        ~Free() { (void)hipFree(q); }
-    } free_adv{adv};
+        double** t;
+        ~Free()
+        {
+            (void)hipFree(q);
+            (void)hipFree(*t);
+            *t = nullptr;
+        }
+    } free_adv{adv, &p->tune_u};
     HIPCHK(hipMemcpyAsync(adv, u, bytes, hipMemcpyDeviceToDevice, s));
     st = prologue(p, adv, n0, s);
     if (!st) st = run_steps(p, adv, n0, kTuneWarm, 0, nullptr, s);
