@@ -91,6 +91,28 @@ def test_1d_ties_lowest_offset(torch_dev, orc):
     assert np.array_equal(arg.cpu().numpy().astype(np.int32), refarg)
 
 
+@pytest.mark.parametrize("N,tau", [(300007, 1e-5), (600001, 1e-5), ((1 << 21) + 12345, 1e-7)])
+def test_1d_long_lines_fast(torch_dev, orc, N, tau):
+    """One long line, fast path, 4 steps with the potential: tiles of 1024
+    targets in blocks of 512 threads (300007 points, a ragged last tile) and of
+    256 threads (600001 points; 2^21 + 12345 points, 2061 tiles, more than the
+    2048 resident at once, where the next step's window search runs after a
+    tile instead of in a block of its own); tau V is prefetched for 2 or 4
+    targets a thread.
+    Small amplitudes and tau keep the oracle's candidate interval (from the
+    oscillation) to a few hundred offsets."""
+    torch = torch_dev
+    steps, P = 4, 0.3
+    print_case("1d long line", N, tau)
+    u0 = 2e-3 * (wl.smooth_grid([N], 31) + 0.1 * wl.random_grid([N], 32))
+    V = 1e-3 * wl.smooth_grid([N], 33)
+    ref = orc.run(u0, tau, [P], steps, V=V)
+    p = _plan(torch, [N], tau, [P], V, "fast")
+    u = _gpu(torch, u0)
+    p.run(u, steps)
+    _check(u.cpu().numpy(), ref, "fast")
+
+
 # ------------------------------------------------------------------ 2-D ----
 @pytest.mark.parametrize("method", ["brute", "fast"])
 @pytest.mark.parametrize("n", [(96, 80), (130, 257), (16, 300)])
