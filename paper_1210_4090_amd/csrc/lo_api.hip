@@ -124,7 +124,7 @@ void fold_slot(const uint64_t* raw, double* out)
 {
     for (int w = 0; w < kSlotWords; w++) {
         double m = -INFINITY;
-        for (int j = 0; j < kSpread; j++) m = std::max(m, host_dec(raw[w * kSpread + j]));
+        for (int j = 0; j < kSpread; j++) m = std::max(m, host_dec(raw[stat_index(w, j)]));
         out[w] = m;
     }
 }

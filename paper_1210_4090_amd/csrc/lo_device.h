@@ -192,7 +192,7 @@ __device__ __forceinline__ void clear_slot(uint64_t* slot)
 // Fold a value into word `w` of a stats slot (sub-slot chosen by the block).
 __device__ __forceinline__ void stat_put(uint64_t* slot, int w, double v)
 {
-    atomicMax((unsigned long long*)&slot[w * kSpread + (int)(blockIdx.x % kSpread)], (unsigned long long)enc(v));
+    atomicMax((unsigned long long*)&slot[stat_index(w, (int)(blockIdx.x % kSpread))], (unsigned long long)enc(v));
 }
 
 // A wave-uniform 64-bit value moved to scalar registers, so that pointers
@@ -332,7 +332,7 @@ __device__ inline void next_windows(const WinParams& Pg, int64_t inst, const uin
 #pragma unroll
         for (int i = 0; i < 3; i++) {
             const int k = w + i * nwv;
-            v[i] = k < kWords ? slot[k * kSpread + lane] : 0;
+            v[i] = k < kWords ? slot[stat_index(k, lane)] : 0;
         }
         uint64_t pw = 0;
         if (w == 0 && lane < kParamWords) __builtin_memcpy(&pw, (const char*)&Pg + 8 * lane, 8);

@@ -16,7 +16,12 @@ constexpr int kSlotWords = 10;     // per slot: [a] max fwd diff, [3+a] max -fwd
                                    // [7] max u, [8] max -u of the step result
 constexpr int kSpread = 64;        // each word is spread over 64 sub-slots (block index mod 64) so
                                    // that thousands of blocks do not contend on one atomic address
-constexpr int kSlotStride = kSlotWords * kSpread;   // word w, sub-slot j at [w * kSpread + j]
+constexpr int kSubStride = 16;     // a sub-slot holds its words in one 128-byte line: the blocks'
+                                   // atomics on a word go to 64 lines (and L2 channels), not 5
+constexpr int kSlotStride = kSpread * kSubStride;
+static_assert(kSlotWords <= kSubStride, "a sub-slot's words fit its line");
+// word w of sub-slot j of a statistics slot
+__host__ __device__ constexpr int stat_index(int w, int j) { return j * kSubStride + w; }
 
 // error bits latched in flags[0]
 constexpr uint32_t kErrWindowCap = 1u;    // computed window exceeded the kinetic table
