@@ -67,6 +67,24 @@ def test_small_batch_matches_oracle(torch_dev, orc, method):
         assert out[i][0] <= out[i][1] <= out[i][2]
 
 
+def test_small_odd_sides_one_line_tiles(torch_dev, orc):
+    """Sides below 16 and not multiples of 8: both axes sweep in one-line
+    tiles, and each instance's next windows come from a search block of its
+    own (block 0 of its row of the launch grid)."""
+    torch = torch_dev
+    from paper_1210_4090_amd.lo import effective_H
+    bw = wl.config4(ninst_p1=3, ninst_p2=2, sides=(10, 12, 14), tau=0.1, T=3.0, seed=13)
+    bw.P = bw.P * 3.0
+    print_case("hbar one-line tiles", bw.ninst)
+    Vd = _V_dev(torch, bw)
+    out = effective_H(bw.sides, bw.P, Vd, bw.tau, bw.T, method="fast")
+    for i in range(bw.ninst):
+        s = int(bw.sides[i])
+        ref = _oracle_bracket(orc, s, bw.P[i], bw.V_by_side[s], bw.tau, bw.T)
+        _fast_check("one-line tiles instance %d (side %d)" % (i, s), out[i], ref)
+        assert out[i][0] <= out[i][1] <= out[i][2]
+
+
 def test_zero_rotation_gives_max_potential(torch_dev):
     """P = 0: the cheapest cycle rests at the maximum of V (zero kinetic
     cost), so the discrete effective Hamiltonian is max V on the grid and
