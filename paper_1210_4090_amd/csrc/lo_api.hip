@@ -1521,25 +1521,47 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
     std::vector<uint32_t> am((size_t)seg * p->ndim);
     // Segment k recomputed from its checkpoint (on s2) with every sweep's
     // argmins in buffer k % 2; each step's largest offsets size its scatter
-    // tiles.
-    auto recompute = [&](int64_t k) -> lo_status {
-        const int64_t n0 = k * ckpt_every, n1 = std::min(nsteps, n0 + ckpt_every);
+    // tiles.  Enqueued in two parts: the checkpoint, the prologue and the
+    // first kGraphSteps steps go ahead of the reverse sweeps of the segment
+    // after it (so that s2, the longer chain, starts at once); the rest, after
+    // each kGraphSteps steps' halo update (a host wait), goes behind them.
+    auto seg_of = [&](int64_t k, int64_t* n0, int64_t* n1) {
+        *n0 = k * ckpt_every;
+        *n1 = std::min(nsteps, *n0 + ckpt_every);
+    };
+    auto seg_steps = [&](int64_t k, int64_t from, int64_t to) -> lo_status {
+        int64_t n0, n1;
+        seg_of(k, &n0, &n1);
         int16_t* E = p->bw_arg + (size_t)(k % 2) * seg_arg;
         uint32_t* AM = p->bw_amax + (size_t)(k % 2) * seg * p->ndim * kSpread;
-        const size_t am_words = (size_t)(n1 - n0) * p->ndim;
-        HIPCHK(hipMemcpyAsync(p->bw_u, ckpt + (size_t)k * p->npts, bytes, hipMemcpyDeviceToDevice, s2));
-        HIPCHK(launch_fill_u32(AM, (int64_t)(am_words * kSpread), 0u, s2));
-        lo_status r = prologue(p, p->bw_u, n0, s2);
         // every recompute but the first runs beside the scatters of the segment
         // after it: its sweeps leave room for them on every CU
         p->narrow = n1 < nsteps;
-        for (int64_t n = n0; n < n1 && !r; n++) {
+        lo_status r = LO_OK;
+        for (int64_t n = from; n < to && !r; n++) {
             if (n > n0 && (n - n0) % kGraphSteps == 0) r = adapt_from_flags(p, s2);
             if (!r)
                 r = enqueue_step(p, p->bw_u, n, E + (size_t)(n - n0) * p->ndim * p->npts, s2, nullptr,
                                  AM + (n - n0) * p->ndim * kSpread);
         }
         p->narrow = false;
+        return r;
+    };
+    auto recompute_start = [&](int64_t k) -> lo_status {
+        int64_t n0, n1;
+        seg_of(k, &n0, &n1);
+        uint32_t* AM = p->bw_amax + (size_t)(k % 2) * seg * p->ndim * kSpread;
+        HIPCHK(hipMemcpyAsync(p->bw_u, ckpt + (size_t)k * p->npts, bytes, hipMemcpyDeviceToDevice, s2));
+        HIPCHK(launch_fill_u32(AM, (int64_t)((n1 - n0) * p->ndim * kSpread), 0u, s2));
+        lo_status r = prologue(p, p->bw_u, n0, s2);
+        return r ? r : seg_steps(k, n0, std::min(n1, n0 + kGraphSteps));
+    };
+    auto recompute_finish = [&](int64_t k) -> lo_status {
+        int64_t n0, n1;
+        seg_of(k, &n0, &n1);
+        uint32_t* AM = p->bw_amax + (size_t)(k % 2) * seg * p->ndim * kSpread;
+        const size_t am_words = (size_t)(n1 - n0) * p->ndim;
+        lo_status r = seg_steps(k, std::min(n1, n0 + kGraphSteps), n1);
         if (r) return r;
         uint32_t* f = host_words(p, kFlagWords + am_words * kSpread);
         if (!f) return LO_ERR_HIP;
@@ -1560,18 +1582,21 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
     // s) run while segment k - 1 is recomputed (on s2) into the other buffer,
     // which the reverse sweeps of segment k + 1 have released.
     const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
-    if (nseg > 0) st = recompute(nseg - 1);
+    if (nseg > 0) st = recompute_start(nseg - 1);
+    if (nseg > 0 && !st) st = recompute_finish(nseg - 1);
     for (int64_t k = nseg - 1; k >= 0 && !st; k--) {
         const int64_t n0 = k * ckpt_every, n1 = std::min(nsteps, n0 + ckpt_every);
+        if (k > 0) {
+            if (k + 1 < nseg) HIPCHK(hipStreamWaitEvent(s2, p->bw_ev[3 + (k + 1) % 2], 0));
+            st = recompute_start(k - 1);
+            if (st) break;
+        }
         HIPCHK(hipStreamWaitEvent(s, p->bw_ev[1 + k % 2], 0));
         st = reverse_steps(p, p->bw_arg + (size_t)(k % 2) * seg_arg, n0, n1, sa[k % 2].data(), &cur,
                            grad_coef != nullptr, s);
         if (st) break;
         HIPCHK(hipEventRecord(p->bw_ev[3 + k % 2], s));
-        if (k > 0) {
-            if (k + 1 < nseg) HIPCHK(hipStreamWaitEvent(s2, p->bw_ev[3 + (k + 1) % 2], 0));
-            st = recompute(k - 1);
-        }
+        if (k > 0) st = recompute_finish(k - 1);
     }
     // a window or argmin error of a recompute is reported through errs
     if (st == LO_ERR_WINDOW && (errs & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrArgRange))) st = LO_OK;
