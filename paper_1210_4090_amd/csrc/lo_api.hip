@@ -101,6 +101,10 @@ struct lo_plan_s {
     uint32_t* hpin = nullptr;
     size_t hpin_words = 0;
     bool narrow = false;             // sweeps at one block a CU (the reverse pass's recompute)
+    // lo_run in the steady state: each segment's window maxima read back
+    // behind it (two pinned buffers of 3 kSpread words, their events)
+    uint32_t* seg_pin = nullptr;
+    hipEvent_t seg_ev[2] = {nullptr, nullptr};
     hipStream_t bw_stream = nullptr; // lo_backward: segment recomputes, beside the reverse sweeps
     hipEvent_t bw_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // start, recomputed[2], reversed[2]
     double* bw_part = nullptr;       // projection partial sums [nmodes][blocks] + [nmodes]
@@ -194,6 +198,9 @@ void free_plan(lo_plan_t p)
     if (p->bw_err) (void)hipFree(p->bw_err);
     if (p->bw_amax) (void)hipFree(p->bw_amax);
     if (p->hpin) (void)hipHostFree(p->hpin);
+    if (p->seg_pin) (void)hipHostFree(p->seg_pin);
+    for (auto& e : p->seg_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto& e : p->bw_ev)
         if (e) (void)hipEventDestroy(e);
     if (p->bw_stream) (void)hipStreamDestroy(p->bw_stream);
@@ -1114,6 +1121,23 @@ lo_status run_steps(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t 
     int64_t warm = 2;
     int wl[kMaxDim];
     for (int a = 0; a < kMaxDim; a++) wl[a] = p->wseg[a];
+    // Past the warm-up, a segment is launched without waiting for the one
+    // before it: each segment's window maxima are read back (pinned) behind
+    // it, and the halos of segment i + 2 come from those of segment i (the
+    // halos choose kernel paths, never values).
+    const size_t wwords = (size_t)kMaxDim * kSpread;
+    int pend = -1;   // read-back buffer not yet folded
+    auto fold_seg = [&](int b, bool halos) {
+        const uint32_t* w = p->seg_pin + (size_t)b * wwords;
+        for (int a = 0; a < p->ndim; a++) {
+            const uint32_t wu = fold_spread(w + (size_t)a * kSpread);
+            p->hflags[1 + a] = std::max(p->hflags[1 + a], wu);
+            if (halos) {
+                p->halo[a] = choose_halo(p, a, (int)wu);
+                p->wseg[a] = (int)wu;
+            }
+        }
+    };
     int64_t done = 0;
     while (done < nsteps) {
         const int64_t seg = std::min<int64_t>(warm > 0 ? warm : kGraphSteps, nsteps - done);
@@ -1133,21 +1157,43 @@ lo_status run_steps(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t 
             }
         }
         done += seg;
-        if (done < nsteps) {
+        if (done < nsteps && warm == 0) {
+            if (!p->seg_pin && hipHostMalloc((void**)&p->seg_pin, sizeof(uint32_t) * 2 * wwords,
+                                             hipHostMallocDefault) != hipSuccess) {
+                p->seg_pin = nullptr;
+                return LO_ERR_HIP;
+            }
+            for (auto& e : p->seg_ev)
+                if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            const int b = pend == 0 ? 1 : 0;
+            HIPCHK(hipMemcpyAsync(p->seg_pin + (size_t)b * wwords, p->flags + kFlagWin, sizeof(uint32_t) * wwords,
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(p->seg_ev[b], s));
+            HIPCHK(launch_fill_u32(p->flags + kFlagWin, (int64_t)wwords, 0u, s));
+            if (pend >= 0) {
+                HIPCHK(hipEventSynchronize(p->seg_ev[pend]));
+                fold_seg(pend, true);
+            }
+            pend = b;
+        } else if (done < nsteps) {
             st = adapt_from_flags(p, s);
             if (st) return st;
-            if (warm > 0) {
-                const int64_t next = std::min<int64_t>(2 * warm, 16);
-                bool grows = false;
-                for (int a = 0; a < p->ndim; a++) {
-                    const int64_t d = (int64_t)p->wseg[a] - wl[a];
-                    if (d * kGraphSteps > 8 * seg) grows = true;   // would outgrow half the slack in a segment
-                    if (d > 0) p->halo[a] = choose_halo(p, a, (int)std::min<int64_t>(p->wseg[a] + d * next / seg, 1 << 30));
-                    wl[a] = p->wseg[a];
-                }
-                warm = grows ? next : 0;
+            const int64_t next = std::min<int64_t>(2 * warm, 16);
+            bool grows = false;
+            for (int a = 0; a < p->ndim; a++) {
+                const int64_t d = (int64_t)p->wseg[a] - wl[a];
+                if (d * kGraphSteps > 8 * seg) grows = true;   // would outgrow half the slack in a segment
+                if (d > 0) p->halo[a] = choose_halo(p, a, (int)std::min<int64_t>(p->wseg[a] + d * next / seg, 1 << 30));
+                wl[a] = p->wseg[a];
             }
+            warm = grows ? next : 0;
         }
+    }
+    // the last segment's maxima stay in the flags (the caller's finish reads
+    // them); a read-back still pending is folded into the run's maxima
+    if (pend >= 0) {
+        HIPCHK(hipEventSynchronize(p->seg_ev[pend]));
+        fold_seg(pend, false);
     }
     return LO_OK;
 }
