@@ -644,7 +644,10 @@ lo_status enqueue_step(lo_plan_t p, double* u, int64_t n, int16_t* argmin, hipSt
     return LO_OK;
 }
 
-lo_status prologue(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
+// wait: read the first windows back and size the halos from them (a host
+// wait); otherwise the halos stay as they are (they choose kernel paths,
+// never values) and the first windows are left in the flags' maxima
+lo_status prologue(lo_plan_t p, const double* u, int64_t n0, hipStream_t s, bool wait = true)
 {
     HIPCHK(hipMemsetAsync(p->flags, 0, sizeof(uint32_t) * kFlagWords, s));
     HIPCHK(launch_clear_slots(p->stats, p->nb, s));
@@ -654,7 +657,7 @@ lo_status prologue(lo_plan_t p, const double* u, int64_t n0, hipStream_t s)
     // compute for the following steps), halos from their maximum
     HIPCHK(launch_windows(p->winp, slot(p, n0), p->win + (size_t)(((n0 % 2) + 2) % 2) * 2 * kMaxDim, p->flags, p->nb,
                           s));
-    return adapt_from_flags(p, s);
+    return wait ? adapt_from_flags(p, s) : LO_OK;
 }
 
 lo_status finish(lo_plan_t p, hipStream_t s, bool argmin)
@@ -1569,8 +1572,9 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
     // argmins in buffer k % 2; each step's largest offsets size its scatter
     // tiles.  Enqueued in two parts: the checkpoint, the prologue and the
     // first kGraphSteps steps go ahead of the reverse sweeps of the segment
-    // after it (so that s2, the longer chain, starts at once); the rest, after
-    // each kGraphSteps steps' halo update (a host wait), goes behind them.
+    // after it (so that s2, the longer chain, starts at once), the rest behind
+    // them; no part waits on the host before the read-back at its end (the
+    // halos carry over from the segment before, sized by its windows).
     auto seg_of = [&](int64_t k, int64_t* n0, int64_t* n1) {
         *n0 = k * ckpt_every;
         *n1 = std::min(nsteps, *n0 + ckpt_every);
@@ -1584,12 +1588,9 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
         // after it: its sweeps leave room for them on every CU
         p->narrow = n1 < nsteps;
         lo_status r = LO_OK;
-        for (int64_t n = from; n < to && !r; n++) {
-            if (n > n0 && (n - n0) % kGraphSteps == 0) r = adapt_from_flags(p, s2);
-            if (!r)
-                r = enqueue_step(p, p->bw_u, n, E + (size_t)(n - n0) * p->ndim * p->npts, s2, nullptr,
-                                 AM + (n - n0) * p->ndim * kSpread);
-        }
+        for (int64_t n = from; n < to && !r; n++)
+            r = enqueue_step(p, p->bw_u, n, E + (size_t)(n - n0) * p->ndim * p->npts, s2, nullptr,
+                             AM + (n - n0) * p->ndim * kSpread);
         p->narrow = false;
         return r;
     };
@@ -1599,7 +1600,7 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
         uint32_t* AM = p->bw_amax + (size_t)(k % 2) * seg * p->ndim * kSpread;
         HIPCHK(hipMemcpyAsync(p->bw_u, ckpt + (size_t)k * p->npts, bytes, hipMemcpyDeviceToDevice, s2));
         HIPCHK(launch_fill_u32(AM, (int64_t)((n1 - n0) * p->ndim * kSpread), 0u, s2));
-        lo_status r = prologue(p, p->bw_u, n0, s2);
+        lo_status r = prologue(p, p->bw_u, n0, s2, false);
         return r ? r : seg_steps(k, n0, std::min(n1, n0 + kGraphSteps));
     };
     auto recompute_finish = [&](int64_t k) -> lo_status {
@@ -1618,7 +1619,12 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
         for (size_t i = 0; i < am_words; i++) am[i] = fold_spread(am_raw + i * kSpread);
         errs |= f[0];
         if (f[0] & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrArgRange)) return LO_ERR_WINDOW;
-        for (int a = 0; a < p->ndim; a++) hf[1 + a] = std::max(hf[1 + a], std::max(p->hflags[1 + a], fold_window(f, a)));
+        for (int a = 0; a < p->ndim; a++) {
+            const uint32_t wu = fold_window(f, a);
+            hf[1 + a] = std::max(hf[1 + a], std::max(p->hflags[1 + a], wu));
+            p->halo[a] = choose_halo(p, a, (int)wu);   // for the segment recomputed next
+            p->wseg[a] = (int)wu;
+        }
         for (size_t i = 0; i < am_words; i++) hf[4 + i % p->ndim] = std::max(hf[4 + i % p->ndim], am[i]);
         HIPCHK(hipEventRecord(p->bw_ev[1 + k % 2], s2));
         sa[k % 2].resize(am_words);
