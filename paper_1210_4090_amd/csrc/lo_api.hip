@@ -1112,6 +1112,64 @@ lo_status get_graph(lo_plan_t p, double* u, int64_t n0, hipGraphExec_t* out)
 
 // The step loop of lo_run after its prologue.  It may return with segments
 // still running on s (the caller drains the stream on error).
+// The halo update of a step loop without a host wait: behind each segment
+// its window maxima are copied into pinned memory (an event marks the copy)
+// and the window words cleared; the copy of the segment before is folded in
+// meanwhile, so a segment's halos come from the windows two segments back
+// (halos choose kernel paths, never values).
+struct LaggedAdapt {
+    lo_plan_t p;
+    hipStream_t s;
+    int pend = -1;   // read-back buffer not yet folded
+    static constexpr size_t kWords = (size_t)kMaxDim * kSpread;
+
+    void fold(int b, bool halos)
+    {
+        const uint32_t* w = p->seg_pin + (size_t)b * kWords;
+        for (int a = 0; a < p->ndim; a++) {
+            const uint32_t wu = fold_spread(w + (size_t)a * kSpread);
+            p->hflags[1 + a] = std::max(p->hflags[1 + a], wu);
+            if (halos) {
+                p->halo[a] = choose_halo(p, a, (int)wu);
+                p->wseg[a] = (int)wu;
+            }
+        }
+    }
+    // after a segment that another one follows
+    lo_status segment_done()
+    {
+        if (!p->seg_pin &&
+            hipHostMalloc((void**)&p->seg_pin, sizeof(uint32_t) * 2 * kWords, hipHostMallocDefault) != hipSuccess) {
+            p->seg_pin = nullptr;
+            return LO_ERR_HIP;
+        }
+        for (auto& e : p->seg_ev)
+            if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        const int b = pend == 0 ? 1 : 0;
+        HIPCHK(hipMemcpyAsync(p->seg_pin + (size_t)b * kWords, p->flags + kFlagWin, sizeof(uint32_t) * kWords,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(p->seg_ev[b], s));
+        HIPCHK(launch_fill_u32(p->flags + kFlagWin, (int64_t)kWords, 0u, s));
+        if (pend >= 0) {
+            HIPCHK(hipEventSynchronize(p->seg_ev[pend]));
+            fold(pend, true);
+        }
+        pend = b;
+        return LO_OK;
+    }
+    // at the loop's end: the last segment's maxima stay in the flags (finish
+    // reads them); a copy still pending joins the run's maxima
+    lo_status end()
+    {
+        if (pend >= 0) {
+            HIPCHK(hipEventSynchronize(p->seg_ev[pend]));
+            fold(pend, false);
+            pend = -1;
+        }
+        return LO_OK;
+    }
+};
+
 lo_status run_steps(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t ckpt_every, double* ckpt,
                     hipStream_t s)
 {
@@ -1124,23 +1182,8 @@ lo_status run_steps(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t 
     int64_t warm = 2;
     int wl[kMaxDim];
     for (int a = 0; a < kMaxDim; a++) wl[a] = p->wseg[a];
-    // Past the warm-up, a segment is launched without waiting for the one
-    // before it: each segment's window maxima are read back (pinned) behind
-    // it, and the halos of segment i + 2 come from those of segment i (the
-    // halos choose kernel paths, never values).
-    const size_t wwords = (size_t)kMaxDim * kSpread;
-    int pend = -1;   // read-back buffer not yet folded
-    auto fold_seg = [&](int b, bool halos) {
-        const uint32_t* w = p->seg_pin + (size_t)b * wwords;
-        for (int a = 0; a < p->ndim; a++) {
-            const uint32_t wu = fold_spread(w + (size_t)a * kSpread);
-            p->hflags[1 + a] = std::max(p->hflags[1 + a], wu);
-            if (halos) {
-                p->halo[a] = choose_halo(p, a, (int)wu);
-                p->wseg[a] = (int)wu;
-            }
-        }
-    };
+    // past the warm-up the halo update does not wait for the stream
+    LaggedAdapt lag{p, s};
     int64_t done = 0;
     while (done < nsteps) {
         const int64_t seg = std::min<int64_t>(warm > 0 ? warm : kGraphSteps, nsteps - done);
@@ -1161,23 +1204,8 @@ lo_status run_steps(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t 
         }
         done += seg;
         if (done < nsteps && warm == 0) {
-            if (!p->seg_pin && hipHostMalloc((void**)&p->seg_pin, sizeof(uint32_t) * 2 * wwords,
-                                             hipHostMallocDefault) != hipSuccess) {
-                p->seg_pin = nullptr;
-                return LO_ERR_HIP;
-            }
-            for (auto& e : p->seg_ev)
-                if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-            const int b = pend == 0 ? 1 : 0;
-            HIPCHK(hipMemcpyAsync(p->seg_pin + (size_t)b * wwords, p->flags + kFlagWin, sizeof(uint32_t) * wwords,
-                                  hipMemcpyDeviceToHost, s));
-            HIPCHK(hipEventRecord(p->seg_ev[b], s));
-            HIPCHK(launch_fill_u32(p->flags + kFlagWin, (int64_t)wwords, 0u, s));
-            if (pend >= 0) {
-                HIPCHK(hipEventSynchronize(p->seg_ev[pend]));
-                fold_seg(pend, true);
-            }
-            pend = b;
+            st = lag.segment_done();
+            if (st) return st;
         } else if (done < nsteps) {
             st = adapt_from_flags(p, s);
             if (st) return st;
@@ -1192,13 +1220,7 @@ lo_status run_steps(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int64_t 
             warm = grows ? next : 0;
         }
     }
-    // the last segment's maxima stay in the flags (the caller's finish reads
-    // them); a read-back still pending is folded into the run's maxima
-    if (pend >= 0) {
-        HIPCHK(hipEventSynchronize(p->seg_ev[pend]));
-        fold_seg(pend, false);
-    }
-    return LO_OK;
+    return lag.end();
 }
 
 }  // namespace
@@ -1661,10 +1683,12 @@ lo_status lo_run_record(lo_plan_t p, double* u, int64_t n0, int64_t nsteps, int1
     hipStream_t s = (hipStream_t)stream;
     StreamDrain drain{s};
     lo_status st = prologue(p, u, n0, s);
+    LaggedAdapt lag{p, s};
     for (int64_t k = 0; k < nsteps && !st; k++) {
-        if (k > 0 && k % kGraphSteps == 0) st = adapt_from_flags(p, s);
+        if (k > 0 && k % kGraphSteps == 0) st = lag.segment_done();
         if (!st) st = enqueue_step(p, u, n0 + k, argmins + (size_t)k * p->ndim * p->npts, s);
     }
+    if (!st) st = lag.end();
     if (st) return st;
     return finish(p, s, true);
 }
