@@ -1625,52 +1625,80 @@ lo_status lo_backward(lo_plan_t p, const double* ckpt, int64_t nsteps, int64_t c
         lo_status r = prologue(p, p->bw_u, n0, s2, false);
         return r ? r : seg_steps(k, n0, std::min(n1, n0 + kGraphSteps));
     };
-    auto recompute_finish = [&](int64_t k) -> lo_status {
+    // The rest of segment k and its read-back (flags and offset maxima into
+    // the pinned slot k % 2), then the event that marks it recomputed.
+    const size_t rb_words = kFlagWords + (size_t)seg * p->ndim * kSpread;
+    uint32_t* rb = host_words(p, 2 * rb_words);
+    if (!rb) return LO_ERR_HIP;
+    auto recompute_rest = [&](int64_t k) -> lo_status {
         int64_t n0, n1;
         seg_of(k, &n0, &n1);
         uint32_t* AM = p->bw_amax + (size_t)(k % 2) * seg * p->ndim * kSpread;
         const size_t am_words = (size_t)(n1 - n0) * p->ndim;
         lo_status r = seg_steps(k, std::min(n1, n0 + kGraphSteps), n1);
         if (r) return r;
-        uint32_t* f = host_words(p, kFlagWords + am_words * kSpread);
-        if (!f) return LO_ERR_HIP;
-        uint32_t* am_raw = f + kFlagWords;
+        uint32_t* f = rb + (size_t)(k % 2) * rb_words;
         HIPCHK(hipMemcpyAsync(f, p->flags, sizeof(uint32_t) * kFlagWords, hipMemcpyDeviceToHost, s2));
-        HIPCHK(hipMemcpyAsync(am_raw, AM, sizeof(uint32_t) * am_words * kSpread, hipMemcpyDeviceToHost, s2));
-        HIPCHK(hipStreamSynchronize(s2));
-        for (size_t i = 0; i < am_words; i++) am[i] = fold_spread(am_raw + i * kSpread);
+        HIPCHK(hipMemcpyAsync(f + kFlagWords, AM, sizeof(uint32_t) * am_words * kSpread, hipMemcpyDeviceToHost,
+                              s2));
+        HIPCHK(hipEventRecord(p->bw_ev[1 + k % 2], s2));
+        return LO_OK;
+    };
+    // The host's part of segment k once its read-back has landed: errors,
+    // window and offset maxima, halos for the segments recomputed later, and
+    // the scatter layouts.
+    auto recompute_wait = [&](int64_t k) -> lo_status {
+        int64_t n0, n1;
+        seg_of(k, &n0, &n1);
+        const size_t am_words = (size_t)(n1 - n0) * p->ndim;
+        HIPCHK(hipEventSynchronize(p->bw_ev[1 + k % 2]));
+        const uint32_t* f = rb + (size_t)(k % 2) * rb_words;
+        for (size_t i = 0; i < am_words; i++) am[i] = fold_spread(f + kFlagWords + i * kSpread);
         errs |= f[0];
         if (f[0] & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrArgRange)) return LO_ERR_WINDOW;
         for (int a = 0; a < p->ndim; a++) {
             const uint32_t wu = fold_window(f, a);
             hf[1 + a] = std::max(hf[1 + a], std::max(p->hflags[1 + a], wu));
-            p->halo[a] = choose_halo(p, a, (int)wu);   // for the segment recomputed next
+            p->halo[a] = choose_halo(p, a, (int)wu);
             p->wseg[a] = (int)wu;
         }
         for (size_t i = 0; i < am_words; i++) hf[4 + i % p->ndim] = std::max(hf[4 + i % p->ndim], am[i]);
-        HIPCHK(hipEventRecord(p->bw_ev[1 + k % 2], s2));
         sa[k % 2].resize(am_words);
         return scatter_layouts(p, am.data(), n1 - n0, sa[k % 2].data());
     };
     // Segments are undone from the last.  The reverse sweeps of segment k (on
     // s) run while segment k - 1 is recomputed (on s2) into the other buffer,
-    // which the reverse sweeps of segment k + 1 have released.
+    // which the reverse sweeps of segment k + 1 have released.  Segment k - 2's
+    // first part is enqueued behind segment k - 1's read-back, before the host
+    // waits for it, so that s2 does not idle between segments.
     const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
     if (nseg > 0) st = recompute_start(nseg - 1);
-    if (nseg > 0 && !st) st = recompute_finish(nseg - 1);
+    if (nseg > 0 && !st) st = recompute_rest(nseg - 1);
+    if (nseg > 0 && !st) st = recompute_wait(nseg - 1);
+    bool started = false;   // segment k - 1's first part already enqueued
     for (int64_t k = nseg - 1; k >= 0 && !st; k--) {
         const int64_t n0 = k * ckpt_every, n1 = std::min(nsteps, n0 + ckpt_every);
-        if (k > 0) {
+        if (k > 0 && !started) {
             if (k + 1 < nseg) HIPCHK(hipStreamWaitEvent(s2, p->bw_ev[3 + (k + 1) % 2], 0));
             st = recompute_start(k - 1);
             if (st) break;
         }
+        started = false;
         HIPCHK(hipStreamWaitEvent(s, p->bw_ev[1 + k % 2], 0));
         st = reverse_steps(p, p->bw_arg + (size_t)(k % 2) * seg_arg, n0, n1, sa[k % 2].data(), &cur,
                            grad_coef != nullptr, s);
         if (st) break;
         HIPCHK(hipEventRecord(p->bw_ev[3 + k % 2], s));
-        if (k > 0) st = recompute_finish(k - 1);
+        if (k > 0) {
+            st = recompute_rest(k - 1);
+            if (!st && k > 1) {
+                // segment k - 2 overwrites buffer k % 2 once the reverse sweeps of k are done
+                HIPCHK(hipStreamWaitEvent(s2, p->bw_ev[3 + k % 2], 0));
+                st = recompute_start(k - 2);
+                started = true;
+            }
+            if (!st) st = recompute_wait(k - 1);
+        }
     }
     // a window or argmin error of a recompute is reported through errs
     if (st == LO_ERR_WINDOW && (errs & (kErrWindowCap | kErrWindowEdge | kErrFastPath | kErrArgRange))) st = LO_OK;
